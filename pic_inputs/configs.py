@@ -1,0 +1,84 @@
+"""Discharge workloads (synthetic, seeded).
+
+The physical set-up follows Sec. II of the paper: a planar 1d3v gap of width L,
+one electrode driven by U(t) = U_rf sin(2 pi f t), the other grounded, both
+perfectly absorbing, O2 reservoir at pressure p and temperature T.
+
+Normalisation (Sec. II): the lateral area is A = lambda_De^2 of a reference
+electron system (n_res, T_res).  The paper quotes n_res ~ 1e8-1e9 cm^-3 and
+k T_res ~ 10 eV; we take n_res = 1e9 cm^-3 and T_res = 10 eV, and give every
+species the same macro weight W = n_res * A * L / N_e(0), so that the initial
+electron load represents n_res.
+
+The three named workloads are the single-discharge cases used for parity and
+measurement:
+  small  -- 4 cm, 128 cells, 10 Pa, 100 V, dt = T_rf/1000, 10k e + 2k O- + 10k O2+
+  prod   -- 4 cm, 1024 cells, 50 Pa, 200 V, dt = T_rf/4000, ions sub-cycled x10,
+            2M e + 0.5M O- + 2M O2+
+  large  -- 6 cm, 4096 cells, 100 Pa, 400 V, dt = T_rf/8000,
+            2^25 macro-particles split 50 % e, 10 % O-, 40 % O2+
+All use 13.56 MHz, a uniform initial load with Maxwellian velocities
+(electrons 3 eV, ions 0.026 eV), C = 1/6 for associative detachment.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+EPS0 = 8.8541878128e-12
+QE = 1.602176634e-19
+
+N_RES = 1.0e15          # m^-3  (1e9 cm^-3)
+T_RES_EV = 10.0
+
+
+def debye_area(n_res=N_RES, t_res_ev=T_RES_EV):
+    """A = lambda_De^2 = eps0 k T_res / (e^2 n_res)."""
+    return EPS0 * t_res_ev / (QE * n_res)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    gap_m: float
+    n_cells: int
+    pressure_Pa: float
+    voltage_V: float
+    frequency_Hz: float
+    steps_per_period: int
+    ion_subcycle: int
+    n_init: tuple            # (electrons, O-, O2+)
+    T_init_eV: tuple = (3.0, 0.026, 0.026)
+    T_gas_K: float = 300.0
+    metastable_frac: float = 1.0 / 6.0
+    sort_every: int = 10
+    seed: int = 705049500
+    area_m2: float = field(default_factory=debye_area)
+    weight: float = 0.0      # 0 -> n_res * A * L / N_e(0)
+
+    def resolved(self) -> "Workload":
+        w = self.weight
+        if w == 0.0:
+            w = N_RES * self.area_m2 * self.gap_m / float(self.n_init[0])
+        return replace(self, weight=w)
+
+    def scaled(self, factor: float, name: str | None = None) -> "Workload":
+        """Same discharge with every initial population scaled by ``factor``;
+        the weight is rescaled so the represented densities stay the same."""
+        base = self.resolved()
+        n = tuple(max(1, int(round(x * factor))) for x in base.n_init)
+        w = base.weight * base.n_init[0] / n[0]
+        return replace(base, n_init=n, weight=w, name=name or f"{base.name}/x{factor:g}")
+
+
+WORKLOADS = {
+    "small": Workload("small", 0.04, 128, 10.0, 100.0, 13.56e6, 1000, 1,
+                      (10_000, 2_000, 10_000), sort_every=10, seed=705049501),
+    "prod": Workload("prod", 0.04, 1024, 50.0, 200.0, 13.56e6, 4000, 10,
+                     (2_000_000, 500_000, 2_000_000), sort_every=100, seed=705049502),
+    "large": Workload("large", 0.06, 4096, 100.0, 400.0, 13.56e6, 8000, 1,
+                      (16_777_216, 3_355_443, 13_421_773), sort_every=10, seed=705049503),
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name].resolved()
