@@ -1,0 +1,168 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) PIC-MCC library for a capacitively
+ * coupled rf discharge in oxygen with electrons, O- and O2+ (Bronold,
+ * Matyash, Tskhakaya, Schneider, Fehske, "Radio-frequency discharges in
+ * Oxygen. Part 1: Modeling").
+ *
+ * The problem statement follows the paper's abstract and Sec. II: for a given
+ * external voltage and pressure the model determines the potential in the gap
+ * and the distribution functions of e, O- and O2+.  A planar gap 0 <= x <= L
+ * (1d3v), one electrode at x = 0 driven by U(t) = U_rf sin(2 pi f t), the
+ * other grounded, both perfectly absorbing, O2 at pressure p and temperature T.
+ *
+ * Every step of the particle path runs in the library's HIP kernels on the
+ * GPU; the host code only sequences launches, owns memory and copies results.
+ *
+ * Conventions
+ *   - Every function returns 0 (PIC_OK) or a negative PIC_E* code.  Errors are
+ *     sticky per context; pic_last_error() returns a message.
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     never keeps them after the call returns and never frees them.  All device
+ *     memory is allocated and freed by the library.
+ *   - One context is used by one host thread at a time.
+ *   - Species indices: 0 = electrons, 1 = O-, 2 = O2+.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK 0
+#define PIC_EINVAL (-1)    /* invalid argument */
+#define PIC_ENOMEM (-2)    /* device allocation failed */
+#define PIC_EDEVICE (-3)   /* HIP runtime error */
+#define PIC_EGUARD (-4)    /* null-collision bound exceeded 1 or non-finite state */
+#define PIC_EOVERFLOW (-5) /* particle, birth or request capacity exceeded */
+
+#define PIC_FP32 0
+#define PIC_FP64 1
+
+#define PIC_NCHAN 19        /* collision channels, numbered as below */
+#define PIC_XS_NPOINTS 897  /* energy nodes E_k = 2^(-14 + k/32) (1 + (k%32)/32) eV */
+
+/*
+ * Channel numbering (Table I of the paper; reaction number in brackets):
+ *   0 e+O2 elastic (4)            1-4 e+O2 vibrational v=1..4 (7)
+ *   5 e+O2 Rydberg (8)            6 e+O2 dissociation 6.4 eV (9)
+ *   7 e+O2 dissociation 8.6 eV (10)  8 e+O2 a1Delta_g (11)  9 e+O2 b1Sigma_g (12)
+ *  10 e+O2 dissociative attachment (15)   11 e+O2 impact ionisation (18)
+ *  12 e+O2+ dissociative recombination (13)  13 e+O- impact detachment (19)
+ *  14 O-+O2 elastic (5)  15 O-+O2 direct detachment (16)
+ *  16 O-+O2(a) associative detachment (17)  17 O-+O2+ neutralisation (14)
+ *  18 O2+ + O2 charge exchange (6)
+ */
+
+typedef struct pic_ctx pic_ctx;
+
+/* Geometry, discretisation and initial load (Sec. II). */
+typedef struct {
+  double gap_m;               /* L */
+  int32_t n_cells;            /* cells of width L/n_cells, 4 <= n_cells <= 8192 */
+  double area_m2;             /* lateral area A (the paper takes lambda_De^2 of a reference system) */
+  double weight;              /* real particles per macro particle, all species */
+  int32_t steps_per_period;   /* dt = 1 / (f * steps_per_period) */
+  int32_t ion_subcycle;       /* ions are moved every ion_subcycle steps with tau = ion_subcycle * dt */
+  int32_t sort_every;         /* particles are re-sorted into cells every sort_every steps */
+  int32_t drive_dc;           /* 0: sinusoidal drive; 1: constant U = voltage (test switch) */
+  int64_t n_init[3];          /* initial macro particles per species */
+  double T_init_eV[3];        /* initial Maxwellian temperatures */
+  uint64_t seed;              /* Philox key */
+  int32_t precision;          /* PIC_FP32 or PIC_FP64 particle state */
+  int64_t capacity[3];        /* store capacity per species; 0 -> 2 n_init + 65536 */
+  int32_t eedf_bins;          /* electron energy histogram at x = L/2, 0 <= bins <= 256 */
+  double eedf_emax_eV;
+  int32_t fneg_xbins;         /* O- f(E,x), E = sign(v_x) M v_x^2 / 2; xbins*ebins <= 2048 */
+  int32_t fneg_ebins;
+  double fneg_emax_eV;
+} pic_geometry;
+
+/* Gas and cross sections (Sec. III). */
+typedef struct {
+  double T_gas_K;             /* reservoir temperature; n_O2 = p / (k T) */
+  double metastable_frac;     /* C: n(O2(a1Delta_g)) = C n_O2 for associative detachment */
+  const double* sigma_m2;     /* host [PIC_NCHAN][PIC_XS_NPOINTS], linear in E between nodes */
+  const double* threshold_eV; /* host [PIC_NCHAN], channel closed below */
+  const double* loss_eV;      /* host [PIC_NCHAN], excitation energy dE of Eq. (5) */
+} pic_gas;
+
+/*
+ * Create a discharge: allocate the particle stores on the current HIP device,
+ * sample the initial load (uniform x, Maxwellian v), deposit, solve the field
+ * at t = 0 and take the leapfrog half step back in velocity.  The call is
+ * synchronous.  Returns PIC_EINVAL for inconsistent inputs, PIC_ENOMEM when
+ * device memory runs out.
+ */
+int pic_create(const pic_geometry* geometry, const pic_gas* gas, double voltage_V, double frequency_Hz,
+               double pressure_Pa, pic_ctx** out);
+
+/* Use this HIP stream (hipStream_t passed as void*) for all later work; NULL = the context's own. */
+int pic_set_stream(pic_ctx* ctx, void* hip_stream);
+
+/*
+ * Enqueue n_steps time steps (asynchronous).  One step: field solve, push and
+ * collisions of every species moved in this step, partner reactions, births
+ * and, every sort_every steps, the cell sort.  Guard conditions raised on the
+ * device are reported by pic_sync.
+ */
+int pic_step(pic_ctx* ctx, int64_t n_steps);
+
+/* Wait for the context's stream; returns PIC_EGUARD / PIC_EOVERFLOW when the device raised one. */
+int pic_sync(pic_ctx* ctx);
+
+/* Moments and diagnostics (synchronising).  Arrays may be NULL when not wanted. */
+typedef struct {
+  int64_t step;               /* steps taken */
+  int64_t cycles;             /* complete rf cycles */
+  int64_t alive[3];           /* macro particles per species */
+  int64_t events[PIC_NCHAN];  /* collision events per channel since creation */
+  int64_t absorbed[2][3];     /* [electrode x=0, x=L][species] */
+  int64_t particle_steps;     /* particles pushed since creation */
+  int64_t births;             /* particles created since creation */
+  int64_t next_id;
+  double* density_m3;         /* host [3][n_cells+1]: last complete rf cycle average */
+  double* phi_V;              /* host [n_cells+1]: last complete rf cycle average */
+  int64_t* eedf;              /* host [eedf_bins+1] counts over the last complete cycle */
+  int64_t* fneg;              /* host [fneg_xbins*fneg_ebins] counts over the last complete cycle */
+} pic_moments_t;
+int pic_moments(pic_ctx* ctx, pic_moments_t* out);
+
+/*
+ * Alive particles of one species (synchronising), in store order.  cap is
+ * the capacity of the caller's arrays (v holds 3*cap doubles); *n_out
+ * receives the number of alive particles even when it exceeds cap.
+ */
+int pic_particles(pic_ctx* ctx, int species, int64_t cap, uint64_t* id_host, int32_t* cell_host,
+                  double* off_host, double* v_host, int64_t* n_out);
+
+/* Potential and field of the last solve, host [n_cells+1] each (synchronising). */
+int pic_field(pic_ctx* ctx, double* phi_host, double* E_host);
+
+/* Node charge of the current alive population, fixed point 2^-24 per macro particle, host [3][n_cells+1]. */
+int pic_charge(pic_ctx* ctx, int64_t* Q_host);
+
+/*
+ * Timing of the fused particle kernel: enable = 1 starts recording HIP events
+ * around every launch of it on the context's stream, enable = 0 stops.
+ * pic_kernel_time syncs and returns the summed duration and the launch count
+ * since the last enable.
+ */
+int pic_timing(pic_ctx* ctx, int enable);
+int pic_kernel_time(pic_ctx* ctx, double* push_ms, int64_t* launches);
+
+/*
+ * Launch shape of the fused particle kernel: number of persistent
+ * workgroups (0 restores the occupancy-derived default).  Results do not
+ * depend on it; the determinism tests vary it.
+ */
+int pic_set_grid(pic_ctx* ctx, int32_t push_workgroups);
+
+int pic_destroy(pic_ctx* ctx);
+const char* pic_last_error(const pic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

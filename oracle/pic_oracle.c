@@ -186,6 +186,7 @@ struct or_ctx {
   int64_t* Q;            /* [3][N+1] */
   /* counters */
   int64_t events[NCH], absorbed[2][3], psteps, births, cycles, tophits, nreq, nacc;
+  int nanflag;
   /* diagnostics */
   int64_t *Qacc, *Qlast, *eedf_acc, *eedf_last, *fneg_acc, *fneg_last;
   double *phiacc, *philast;
@@ -692,6 +693,7 @@ static void push_species(or_ctx* c, int s, uint32_t n) {
     real dxp = p->v[0] * c->dtdx[s];
     real off = p->off + dxp;
     real fl = RFLOOR(off);
+    if (!(fl == fl) || fl > (real)1e9 || fl < (real)-1e9) { p->alive = 0; c->nanflag = 1; continue; }
     int32_t cell = p->cell + (int32_t)fl;
     off = off - fl;
     if (off >= (real)1) { off = 0; cell += 1; }
@@ -877,6 +879,7 @@ static int one_step(or_ctx* c) {
     push_species(c, SP_P, n);
   }
   claims(c, n);
+  if (c->nanflag) return OR_EGUARD;
   int rc = commit_births(c);
   if (rc) return rc;
   if ((c->step + 1) % c->P.sort_every == 0) do_sort(c);

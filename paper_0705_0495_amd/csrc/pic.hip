@@ -1,0 +1,648 @@
+// Host runtime and C ABI of the gfx950 PIC-MCC library (declared in pic.h).
+//
+// The host computes the constants of a discharge once (in double, rounded
+// once to the particle precision), owns the device memory and enqueues the
+// kernels of each step on one HIP stream:
+//   k_field    field solve + diagnostics              (1 workgroup)
+//   k_push     fused gather/push/absorb/MCC/deposit   (persistent grid)
+//   k_claims   partner reactions                      (small grid, exits at once when idle)
+//   k_births   canonical ids, append, close the step  (small grid)
+//   k_sort_*   every sort_every steps
+// Nothing in a step waits for the host.
+#include "pic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic_kernels.hpp"
+
+using namespace pic;
+
+namespace {
+
+const double QE = 1.602176634e-19;
+const double KB = 1.380649e-23;
+const double EPS0 = 8.8541878128e-12;
+const double ME = 9.1093837015e-31;
+const double AMU = 1.66053906660e-27;
+const double TWO_PI_H = 6.283185307179586;
+
+double node_energy(int k) { return std::ldexp(1.0 + (double)(k % 32) / 32.0, -14 + k / 32); }
+
+// upper bound of sum_j sigma_j(E) g(E) on the tabulated range: larger end
+// value of each segment times g at its upper end; constant below the first node
+double bound_sum(const double* sig, const int* ch, int nch, double mu) {
+  const double c2 = (2.0 * QE) / mu;
+  double M = 0.0;
+  double s0 = 0.0;
+  for (int q = 0; q < nch; q++) s0 = s0 + sig[ch[q] * NPT + 0];
+  M = std::max(M, s0 * std::sqrt(node_energy(0) * c2));
+  for (int k = 0; k < NPT - 1; k++) {
+    double s = 0.0;
+    for (int q = 0; q < nch; q++) {
+      double a = sig[ch[q] * NPT + k], b = sig[ch[q] * NPT + k + 1];
+      s = s + (a > b ? a : b);
+    }
+    double v = s * std::sqrt(node_energy(k + 1) * c2);
+    if (v > M) M = v;
+  }
+  return M * (1.0 + 1.0 / 65536.0);
+}
+
+struct Base {
+  virtual ~Base() {}
+  virtual int create() = 0;
+  virtual int step(int64_t n) = 0;
+  virtual int particles(int sp, int64_t cap, uint64_t* id, int32_t* cell, double* off, double* v, int64_t* n) = 0;
+  virtual int field(double* phi, double* E) = 0;
+  virtual int charge(int64_t* Q) = 0;
+  virtual int moments(pic_moments_t* m) = 0;
+  virtual int read_err(int32_t* err) = 0;
+  virtual void set_grid(int g) = 0;
+};
+
+}  // namespace
+
+struct pic_ctx {
+  pic_geometry G;
+  pic_gas gas;
+  std::vector<double> sigma, thr, loss;
+  double U_rf, freq, pres;
+  hipStream_t stream = nullptr;
+  hipStream_t own = nullptr;
+  std::string msg;
+  int err = 0;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t ev_used = 0;
+  double timed_ms = 0;
+  int64_t timed_launches = 0;
+  Base* impl = nullptr;
+};
+
+static int fail(pic_ctx* c, int code, const std::string& m) {
+  if (c) {
+    if (!c->err) {
+      c->err = code;
+      c->msg = m;
+    }
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE,                \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+namespace {
+
+template <class R>
+struct Impl : Base {
+  pic_ctx* c;
+  Consts<R> C;
+  Dev<R> D;
+  std::vector<void*> allocs;
+  int grid_push = 0, grid_push_default = 0, grid_small = 64, grid_scatter = 0;
+  int64_t nstep = 0;  // steps enqueued
+
+  explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
+  ~Impl() override {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <class T>
+  int alloc(T** p, size_t n) {
+    void* q = nullptr;
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(c, PIC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    allocs.push_back(q);
+    e = hipMemsetAsync(q, 0, bytes, c->stream);
+    if (e != hipSuccess) return fail(c, PIC_EDEVICE, "hipMemsetAsync failed");
+    *p = (T*)q;
+    return 0;
+  }
+
+  int alloc_store(Store<R>& s, int64_t cap) {
+    int rc;
+    if ((rc = alloc(&s.cell, cap + 4))) return rc;
+    if ((rc = alloc(&s.off, cap + 4))) return rc;
+    if ((rc = alloc(&s.vx, cap + 4))) return rc;
+    if ((rc = alloc(&s.vy, cap + 4))) return rc;
+    if ((rc = alloc(&s.vz, cap + 4))) return rc;
+    if ((rc = alloc(&s.id, cap + 4))) return rc;
+    return 0;
+  }
+
+  void constants() {
+    const pic_geometry& G = c->G;
+    const int N = G.n_cells;
+    const double dx = G.gap_m / (double)N;
+    const double dt = 1.0 / (c->freq * (double)G.steps_per_period);
+    const double ngas = c->pres / (KB * c->gas.T_gas_K);
+    const double MO2 = 31.998 * AMU;
+    const double mass[3] = {ME, 15.999 * AMU + ME, MO2 - ME};
+    const double charge[3] = {-QE, -QE, QE};
+    const double tau[3] = {dt, dt * (double)G.ion_subcycle, dt * (double)G.ion_subcycle};
+    C.N = N;
+    C.cmid = N / 2;
+    C.M = G.steps_per_period;
+    C.nsub = G.ion_subcycle;
+    C.seed_lo = (uint32_t)G.seed;
+    C.seed_hi = (uint32_t)(G.seed >> 32);
+    double mu_g[3];
+    for (int s = 0; s < 3; s++) {
+      const double qm = charge[s] / mass[s];
+      C.qmdt[s] = (R)(qm * tau[s]);
+      C.dtdx[s] = (R)(tau[s] / dx);
+      C.hk[s] = (R)(qm * (0.5 * tau[s]));
+      C.vth0[s] = (R)std::sqrt((G.T_init_eV[s] * QE) / mass[s]);
+      mu_g[s] = (mass[s] * MO2) / (mass[s] + MO2);
+      C.a_g[s] = (R)(MO2 / (mass[s] + MO2));
+      C.b_g[s] = (R)(mass[s] / (mass[s] + MO2));
+      C.hmu_g[s] = (R)((0.5 * mu_g[s]) / QE);
+      C.c2e_g[s] = (R)((2.0 * QE) / mu_g[s]);
+    }
+    C.vthg = (R)std::sqrt((KB * c->gas.T_gas_K) / MO2);
+    // partner channels 12 (e, O2+), 13 (e, O-), 17 (O-, O2+)
+    const int pch[3] = {12, 13, 17}, ps[3] = {0, 0, 1}, pt[3] = {2, 1, 2};
+    const double* sig = c->sigma.data();
+    for (int q = 0; q < 3; q++) {
+      const double ms = mass[ps[q]], mt = mass[pt[q]];
+      const double mu = (ms * mt) / (ms + mt);
+      C.a_c[q] = (R)(mt / (ms + mt));
+      C.b_c[q] = (R)(ms / (ms + mt));
+      C.hmu_c[q] = (R)((0.5 * mu) / QE);
+      C.c2e_c[q] = (R)((2.0 * QE) / mu);
+      const int one[1] = {pch[q]};
+      const double Mj = bound_sum(sig, one, 1, mu);
+      C.Mr_c[q] = (R)Mj;
+      C.KP[q] = (tau[ps[q]] * Mj) / (G.area_m2 * dx);
+    }
+    C.ddf = (R)std::sqrt((0.1 * mass[1]) / ME);
+    C.adf = (R)std::sqrt(mu_g[1] / ME);
+    C.hme = (R)((0.5 * ME) / QE);
+    C.hmn = (R)((0.5 * mass[1]) / QE);
+    for (int j = 0; j < NCH; j++) {
+      C.thr[j] = (R)c->thr[j];
+      C.loss[j] = (R)c->loss[j];
+      C.PG[j] = 0.0;
+    }
+    for (int j = 0; j < NCH; j++) {
+      if (j == 12 || j == 13 || j == 17) continue;
+      const int s = j <= 11 ? 0 : (j <= 16 ? 1 : 2);
+      C.PG[j] = (j == 16) ? (tau[s] * c->gas.metastable_frac) * ngas : tau[s] * ngas;
+    }
+    const int ge[12] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11}, gn[2] = {14, 15}, gp[1] = {18}, gad[1] = {16};
+    const double Me = bound_sum(sig, ge, 12, mu_g[0]);
+    const double Mn = bound_sum(sig, gn, 2, mu_g[1]);
+    const double Mp = bound_sum(sig, gp, 1, mu_g[2]);
+    const double Mad = bound_sum(sig, gad, 1, mu_g[1]);
+    C.PGtot[0] = C.PG[0] * Me;
+    C.PGtot[1] = C.PG[14] * Mn + C.PG[16] * Mad;
+    C.PGtot[2] = C.PG[18] * Mp;
+    C.cphi = ((dx * QE) * G.weight) / ((EPS0 * 16777216.0) * G.area_m2);
+    C.cE = (QE * G.weight) / ((EPS0 * 16777216.0) * G.area_m2);
+    C.invdx = 1.0 / dx;
+    C.inv2dx = 0.5 / dx;
+    C.eedf_bins = G.eedf_bins;
+    C.fneg_xbins = G.fneg_xbins;
+    C.fneg_ebins = G.fneg_ebins;
+    C.eedf_sc = (R)(G.eedf_bins > 0 ? (double)G.eedf_bins / G.eedf_emax_eV : 0.0);
+    C.fneg_sc = (R)(G.fneg_ebins > 0 ? (double)G.fneg_ebins / (2.0 * G.fneg_emax_eV) : 0.0);
+    C.fneg_em = (R)G.fneg_emax_eV;
+  }
+
+  int create() override {
+    const pic_geometry& G = c->G;
+    const int N = G.n_cells;
+    constants();
+    int rc;
+    for (int s = 0; s < 3; s++) {
+      int64_t cap = G.capacity[s] > 0 ? G.capacity[s] : 2 * G.n_init[s] + 65536;
+      cap = (cap + 3) & ~(int64_t)3;
+      if (cap < G.n_init[s] || cap >= ((int64_t)1 << 31) - 8)
+        return fail(c, PIC_EINVAL, "capacity must hold the initial load and stay below 2^31");
+      D.cap[s] = cap;
+      if ((rc = alloc_store(D.st[s], cap))) return rc;
+      if ((rc = alloc_store(D.alt[s], cap))) return rc;
+    }
+    if ((rc = alloc(&D.N, 3))) return rc;
+    if ((rc = alloc(&D.Nnew, 3))) return rc;
+    if ((rc = alloc(&D.cnt, 3 * (size_t)N))) return rc;
+    if ((rc = alloc(&D.F, 3 * (size_t)N))) return rc;
+    if ((rc = alloc(&D.seg, 3 * (size_t)(N + 1)))) return rc;
+    if ((rc = alloc(&D.cursor, 3 * (size_t)N))) return rc;
+    if ((rc = alloc(&D.segmax, 3))) return rc;
+    if ((rc = alloc(&D.E2, 2 * (size_t)N))) return rc;
+    if ((rc = alloc(&D.phi, (size_t)N + 1))) return rc;
+    if ((rc = alloc(&D.E, (size_t)N + 1))) return rc;
+    double* Ud;
+    if ((rc = alloc(&Ud, (size_t)G.steps_per_period))) return rc;
+    D.U = Ud;
+    R* sg;
+    if ((rc = alloc(&sg, (size_t)NPT * TS))) return rc;
+    D.sig = sg;
+    int64_t totcap = D.cap[0] + D.cap[1] + D.cap[2];
+    D.nb_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(65536, totcap / 32), 1 << 24);
+    if ((rc = alloc(&D.nb, (size_t)D.nb_cap))) return rc;
+    if ((rc = alloc(&D.nbc, 4))) return rc;
+    D.req_cap = REQ_CAP;
+    if ((rc = alloc(&D.req, (size_t)D.req_cap))) return rc;
+    if ((rc = alloc(&D.nreq, 1))) return rc;
+    if ((rc = alloc(&D.ctr, 1))) return rc;
+    if ((rc = alloc(&D.Qacc, 3 * (size_t)(N + 1)))) return rc;
+    if ((rc = alloc(&D.Qlast, 3 * (size_t)(N + 1)))) return rc;
+    if ((rc = alloc(&D.phiacc, (size_t)N + 1))) return rc;
+    if ((rc = alloc(&D.philast, (size_t)N + 1))) return rc;
+    if ((rc = alloc(&D.eedf_acc, (size_t)EEDF_MAX + 1))) return rc;
+    if ((rc = alloc(&D.eedf_last, (size_t)EEDF_MAX + 1))) return rc;
+    if ((rc = alloc(&D.fneg_acc, (size_t)FNEG_MAX))) return rc;
+    if ((rc = alloc(&D.fneg_last, (size_t)FNEG_MAX))) return rc;
+    if ((rc = alloc(&D.done, 4))) return rc;
+
+    // drive table and cross-section table (host math, uploaded once)
+    std::vector<double> U(G.steps_per_period);
+    for (int k = 0; k < G.steps_per_period; k++)
+      U[k] = G.drive_dc ? c->U_rf : c->U_rf * std::sin((TWO_PI_H * (double)k) / (double)G.steps_per_period);
+    std::vector<R> tab((size_t)NPT * TS, (R)0);
+    for (int j = 0; j < NCH; j++)
+      for (int k = 0; k < NPT; k++) tab[(size_t)k * TS + j] = (R)c->sigma[(size_t)j * NPT + k];
+    HIPCHK(c, hipMemcpyAsync(Ud, U.data(), sizeof(double) * U.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sg, tab.data(), sizeof(R) * tab.size(), hipMemcpyHostToDevice, c->stream));
+    Counters h;
+    memset(&h, 0, sizeof(h));
+    h.next_id = G.n_init[0] + G.n_init[1] + G.n_init[2];
+    HIPCHK(c, hipMemcpyAsync(D.ctr, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(D.N, G.n_init, sizeof(int64_t) * 3, hipMemcpyHostToDevice, c->stream));
+
+    // launch shapes
+    int dev = 0, ncu = 0, occ = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
+    grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
+    grid_scatter = std::max(1, ncu * 8);
+
+    // initial load, deposit, field at t = 0, half step back, first sort
+    const int64_t tot = G.n_init[0] + G.n_init[1] + G.n_init[2];
+    if (tot > 0) {
+      const int b = 256;
+      const int g = (int)((tot + b - 1) / b);
+      hipLaunchKernelGGL(k_load<R>, dim3(g), dim3(b), 0, c->stream, C, D, G.n_init[0], G.n_init[1], G.n_init[2]);
+      hipLaunchKernelGGL(k_deposit_all<R>, dim3(g), dim3(b), 0, c->stream, C, D);
+    }
+    hipLaunchKernelGGL(k_field<R>, dim3(1), dim3(FIELD_TPB), 0, c->stream, C, D, 0);
+    if (tot > 0) {
+      const int b = 256;
+      const int g = (int)((tot + b - 1) / b);
+      hipLaunchKernelGGL(k_halfkick<R>, dim3(g), dim3(b), 0, c->stream, C, D);
+    }
+    HIPCHK(c, hipGetLastError());
+    if ((rc = sort())) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int32_t e;
+    if ((rc = read_err(&e))) return rc;
+    return 0;
+  }
+
+  void set_grid(int g) override { grid_push = g > 0 ? g : grid_push_default; }
+
+  int sort() {
+    hipLaunchKernelGGL(k_sort_scan<R>, dim3(3), dim3(SCAN_TPB), 0, c->stream, C, D);
+    hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid_scatter), dim3(256), 0, c->stream, C, D);
+    HIPCHK(c, hipGetLastError());
+    for (int s = 0; s < 3; s++) std::swap(D.st[s], D.alt[s]);
+    return 0;
+  }
+
+  int step(int64_t nsteps) override {
+    const int sort_every = c->G.sort_every;
+    for (int64_t k = 0; k < nsteps; k++) {
+      hipLaunchKernelGGL(k_field<R>, dim3(1), dim3(FIELD_TPB), 0, c->stream, C, D, 1);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c->timing) {
+        if (c->ev_used == c->events.size()) {
+          hipEvent_t a, b;
+          HIPCHK(c, hipEventCreate(&a));
+          HIPCHK(c, hipEventCreate(&b));
+          c->events.push_back({a, b});
+        }
+        e0 = c->events[c->ev_used].first;
+        e1 = c->events[c->ev_used].second;
+        c->ev_used++;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+      }
+      hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
+      if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+      hipLaunchKernelGGL(k_claims<R>, dim3(grid_small), dim3(CLAIM_TPB), 0, c->stream, C, D);
+      hipLaunchKernelGGL(k_births<R>, dim3(grid_small), dim3(BIRTH_TPB), 0, c->stream, C, D);
+      HIPCHK(c, hipGetLastError());
+      nstep++;
+      if (nstep % sort_every == 0) {
+        int rc = sort();
+        if (rc) return rc;
+      }
+      if (c->timing && c->ev_used >= 4096) {
+        int rc = drain_events();
+        if (rc) return rc;
+      }
+    }
+    return 0;
+  }
+
+  int drain_events() {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->ev_used; i++) {
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->events[i].first, c->events[i].second));
+      c->timed_ms += ms;
+      c->timed_launches++;
+    }
+    c->ev_used = 0;
+    return 0;
+  }
+
+  int read_err(int32_t* e) override {
+    Counters h;
+    HIPCHK(c, hipMemcpyAsync(&h, D.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *e = h.err;
+    if (h.err & (ERR_CAP | ERR_NB | ERR_REQ | ERR_ID | ERR_SORT))
+      return fail(c, PIC_EOVERFLOW, "device reported capacity overflow (flags " + std::to_string(h.err) + ")");
+    if (h.err & (ERR_PMAX | ERR_NAN))
+      return fail(c, PIC_EGUARD, "device guard raised (flags " + std::to_string(h.err) + ")");
+    return 0;
+  }
+
+  int particles(int sp, int64_t cap, uint64_t* id, int32_t* cell, double* off, double* v, int64_t* nout) override {
+    int64_t Nh[3];
+    HIPCHK(c, hipMemcpyAsync(Nh, D.N, sizeof(Nh), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t n = Nh[sp];
+    std::vector<int32_t> hc(n);
+    std::vector<R> ho(n), hx(n), hy(n), hz(n);
+    std::vector<uint64_t> hi(n);
+    const Store<R>& s = D.st[sp];
+    if (n > 0) {
+      HIPCHK(c, hipMemcpyAsync(hc.data(), s.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(ho.data(), s.off, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hx.data(), s.vx, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hy.data(), s.vy, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hz.data(), s.vz, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hi.data(), s.id, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; i++) {
+      if (hc[i] == DEAD) continue;
+      if (k < cap) {
+        if (id) id[k] = hi[i];
+        if (cell) cell[k] = hc[i];
+        if (off) off[k] = (double)ho[i];
+        if (v) {
+          v[3 * k] = (double)hx[i];
+          v[3 * k + 1] = (double)hy[i];
+          v[3 * k + 2] = (double)hz[i];
+        }
+      }
+      k++;
+    }
+    *nout = k;
+    return 0;
+  }
+
+  int field(double* phi, double* E) override {
+    const int N = C.N;
+    if (phi) HIPCHK(c, hipMemcpyAsync(phi, D.phi, sizeof(double) * (N + 1), hipMemcpyDeviceToHost, c->stream));
+    if (E) HIPCHK(c, hipMemcpyAsync(E, D.E, sizeof(double) * (N + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+  }
+
+  int charge(int64_t* Q) override {
+    const int N = C.N;
+    std::vector<int32_t> cnt(3 * (size_t)N);
+    std::vector<int64_t> F(3 * (size_t)N);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), D.cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(F.data(), D.F, sizeof(int64_t) * F.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < 3; s++)
+      for (int i = 0; i <= N; i++) {
+        int64_t v = 0;
+        if (i < N) v += ((int64_t)cnt[s * N + i] << 24) - F[s * N + i];
+        if (i >= 1) v += F[s * N + i - 1];
+        Q[s * (N + 1) + i] = v;
+      }
+    return 0;
+  }
+
+  int moments(pic_moments_t* m) override {
+    const int N = C.N;
+    Counters h;
+    int64_t Nh[3];
+    HIPCHK(c, hipMemcpyAsync(&h, D.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Nh, D.N, sizeof(Nh), hipMemcpyDeviceToHost, c->stream));
+    std::vector<int64_t> Q(3 * (size_t)(N + 1));
+    std::vector<double> ph(N + 1);
+    HIPCHK(c, hipMemcpyAsync(Q.data(), D.Qlast, sizeof(int64_t) * Q.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ph.data(), D.philast, sizeof(double) * ph.size(), hipMemcpyDeviceToHost, c->stream));
+    if (m->eedf && c->G.eedf_bins > 0)
+      HIPCHK(c, hipMemcpyAsync(m->eedf, D.eedf_last, sizeof(int64_t) * (c->G.eedf_bins + 1), hipMemcpyDeviceToHost,
+                               c->stream));
+    if (m->fneg && c->G.fneg_xbins * c->G.fneg_ebins > 0)
+      HIPCHK(c, hipMemcpyAsync(m->fneg, D.fneg_last, sizeof(int64_t) * c->G.fneg_xbins * c->G.fneg_ebins,
+                               hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    m->step = h.step;
+    m->cycles = h.cycles;
+    for (int j = 0; j < NCH; j++) m->events[j] = h.events[j];
+    for (int k = 0; k < 6; k++) m->absorbed[k / 3][k % 3] = h.absorbed[k];
+    m->particle_steps = h.psteps;
+    m->births = h.births;
+    m->next_id = h.next_id;
+    // alive counts: the store lengths include dead slots until the next sort
+    for (int s = 0; s < 3; s++) {
+      int64_t tmp = 0;
+      int rc = particles(s, 0, nullptr, nullptr, nullptr, nullptr, &tmp);
+      if (rc) return rc;
+      m->alive[s] = tmp;
+    }
+    const double Mst = (double)c->G.steps_per_period;
+    const double dx = c->G.gap_m / (double)N;
+    if (m->density_m3)
+      for (int s = 0; s < 3; s++)
+        for (int i = 0; i <= N; i++) {
+          const double vol = c->G.area_m2 * dx * ((i == 0 || i == N) ? 0.5 : 1.0);
+          m->density_m3[s * (N + 1) + i] = c->G.weight * ((double)Q[s * (N + 1) + i] / 16777216.0) / vol / Mst;
+        }
+    if (m->phi_V)
+      for (int i = 0; i <= N; i++) m->phi_V[i] = ph[i] / Mst;
+    return 0;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, double frequency_Hz, double pressure_Pa,
+               pic_ctx** out) {
+  if (!out) return PIC_EINVAL;
+  *out = nullptr;
+  if (!g || !gas || !gas->sigma_m2 || !gas->threshold_eV || !gas->loss_eV) return PIC_EINVAL;
+  if (g->n_cells < 4 || g->n_cells > NMAX_CELLS || !(g->gap_m > 0) || !(g->area_m2 > 0) || !(g->weight > 0) ||
+      g->steps_per_period < 1 || g->ion_subcycle < 1 || g->sort_every < 1 || !(frequency_Hz > 0) ||
+      !(pressure_Pa >= 0) || !(gas->T_gas_K > 0) || g->precision < 0 || g->precision > 1 || g->eedf_bins < 0 ||
+      g->eedf_bins > EEDF_MAX || g->fneg_xbins < 0 || g->fneg_ebins < 0 ||
+      (int64_t)g->fneg_xbins * g->fneg_ebins > FNEG_MAX || (g->eedf_bins > 0 && !(g->eedf_emax_eV > 0)) ||
+      (g->fneg_ebins > 0 && !(g->fneg_emax_eV > 0)))
+    return PIC_EINVAL;
+  for (int s = 0; s < 3; s++)
+    if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 31) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;
+  if (g->n_init[0] + g->n_init[1] + g->n_init[2] > (int64_t)(ID_MASK)) return PIC_EINVAL;
+  pic_ctx* c = new pic_ctx();
+  c->G = *g;
+  c->gas = *gas;
+  c->sigma.assign(gas->sigma_m2, gas->sigma_m2 + (size_t)NCH * NPT);
+  c->thr.assign(gas->threshold_eV, gas->threshold_eV + NCH);
+  c->loss.assign(gas->loss_eV, gas->loss_eV + NCH);
+  c->gas.sigma_m2 = c->sigma.data();
+  c->gas.threshold_eV = c->thr.data();
+  c->gas.loss_eV = c->loss.data();
+  c->U_rf = voltage_V;
+  c->freq = frequency_Hz;
+  c->pres = pressure_Pa;
+  for (int j = 0; j < NCH; j++)
+    if (c->thr[j] < c->loss[j]) {
+      delete c;
+      return PIC_EINVAL;
+    }
+  hipError_t e = hipStreamCreate(&c->own);
+  if (e != hipSuccess) {
+    delete c;
+    return PIC_EDEVICE;
+  }
+  c->stream = c->own;
+  if (g->precision == PIC_FP64) c->impl = new Impl<double>(c);
+  else c->impl = new Impl<float>(c);
+  int rc = c->impl->create();
+  if (rc) {
+    delete c->impl;
+    (void)hipStreamDestroy(c->own);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+int pic_set_stream(pic_ctx* c, void* s) {
+  if (!c) return PIC_EINVAL;
+  c->stream = s ? (hipStream_t)s : c->own;
+  return PIC_OK;
+}
+
+int pic_step(pic_ctx* c, int64_t n) {
+  if (!c || n < 0) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->step(n);
+}
+
+int pic_sync(pic_ctx* c) {
+  if (!c) return PIC_EINVAL;
+  if (c->err) return c->err;
+  int32_t e;
+  return c->impl->read_err(&e);
+}
+
+int pic_moments(pic_ctx* c, pic_moments_t* m) {
+  if (!c || !m) return PIC_EINVAL;
+  if (c->err) return c->err;
+  int rc = c->impl->moments(m);
+  if (rc) return rc;
+  return pic_sync(c);
+}
+
+int pic_particles(pic_ctx* c, int sp, int64_t cap, uint64_t* id, int32_t* cell, double* off, double* v,
+                  int64_t* n_out) {
+  if (!c || sp < 0 || sp > 2 || cap < 0 || !n_out) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->particles(sp, cap, id, cell, off, v, n_out);
+}
+
+int pic_field(pic_ctx* c, double* phi, double* E) {
+  if (!c) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->field(phi, E);
+}
+
+int pic_charge(pic_ctx* c, int64_t* Q) {
+  if (!c || !Q) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->charge(Q);
+}
+
+int pic_timing(pic_ctx* c, int enable) {
+  if (!c) return PIC_EINVAL;
+  if (enable) {
+    c->timed_ms = 0;
+    c->timed_launches = 0;
+    c->ev_used = 0;
+  }
+  c->timing = enable != 0;
+  return PIC_OK;
+}
+
+int pic_kernel_time(pic_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return PIC_EINVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, PIC_EDEVICE, hipGetErrorString(e));
+  for (size_t i = 0; i < c->ev_used; i++) {
+    float t = 0;
+    e = hipEventElapsedTime(&t, c->events[i].first, c->events[i].second);
+    if (e != hipSuccess) return fail(c, PIC_EDEVICE, hipGetErrorString(e));
+    c->timed_ms += t;
+    c->timed_launches++;
+  }
+  c->ev_used = 0;
+  *ms = c->timed_ms;
+  *launches = c->timed_launches;
+  return PIC_OK;
+}
+
+int pic_set_grid(pic_ctx* c, int32_t g) {
+  if (!c || g < 0) return PIC_EINVAL;
+  c->impl->set_grid(g);
+  return PIC_OK;
+}
+
+int pic_destroy(pic_ctx* c) {
+  if (!c) return PIC_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  delete c->impl;
+  for (auto& p : c->events) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (c->own) (void)hipStreamDestroy(c->own);
+  delete c;
+  return PIC_OK;
+}
+
+const char* pic_last_error(const pic_ctx* c) {
+  if (!c) return "null context";
+  return c->err ? c->msg.c_str() : "";
+}
+
+}  // extern "C"

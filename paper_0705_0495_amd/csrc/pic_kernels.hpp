@@ -1,0 +1,1273 @@
+// Device code of the gfx950 PIC-MCC step for the oxygen rf discharge
+// (Bronold et al., Sec. II-III).  Included once by pic.hip.
+//
+// Layout in HBM (per species, structure of arrays):
+//   cell  int32   cell index, DEAD for removed particles
+//   off   R       position inside the cell, [0, 1)   (x = (cell + off) dx)
+//   vx, vy, vz R  velocity, m/s (leapfrog: vx at half steps)
+//   id    uint64  particle identity, key of its random streams
+// The field moves only vx and the position, so a particle that does not
+// collide reads cell/off/vx/id and writes cell/off/vx: 20 + 12 bytes (FP32).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int NCH = 19;
+constexpr int NPT = 897;
+constexpr int TS = 20;                 // table row stride: sig[k * TS + channel]
+constexpr int32_t DEAD = INT32_MIN;
+constexpr int TPB = 256;               // threads per push workgroup
+constexpr int PPT = 4;                 // consecutive particles per thread (16-byte vectors)
+constexpr int TILE = TPB * PPT;
+constexpr int WIN = 512;               // cells of the LDS deposit window
+constexpr int EEDF_MAX = 256;
+constexpr int FNEG_MAX = 2048;
+constexpr int REQ_CAP = 4096;          // partner requests per step
+constexpr uint64_t ID_MASK = (1ull << 40) - 1;
+constexpr uint64_t F_MASK = (1ull << 40) - 1;
+constexpr double TWO_PI = 6.283185307179586;
+
+enum : int32_t { ERR_PMAX = 1, ERR_CAP = 2, ERR_NB = 4, ERR_REQ = 8, ERR_ID = 16, ERR_NAN = 32, ERR_SORT = 64 };
+
+// constants of one discharge (computed once on the host, rounded once to R)
+template <class R>
+struct Consts {
+  int32_t N, cmid, M, nsub;
+  uint32_t seed_lo, seed_hi;
+  R qmdt[3], dtdx[3], hk[3], vth0[3];
+  R a_g[3], b_g[3], hmu_g[3], c2e_g[3];
+  R vthg;
+  R a_c[3], b_c[3], hmu_c[3], c2e_c[3], Mr_c[3];   // partner channels 12, 13, 17
+  double KP[3];
+  R ddf, adf, hme, hmn;
+  R thr[NCH], loss[NCH];
+  double PG[NCH];
+  double PGtot[3];
+  double cphi, cE, invdx, inv2dx;
+  int32_t eedf_bins, fneg_xbins, fneg_ebins, pad;
+  R eedf_sc, fneg_sc, fneg_em;
+};
+
+struct Counters {
+  int64_t step, next_id;
+  int64_t events[NCH];
+  int64_t absorbed[6];   // [electrode][species]
+  int64_t psteps, births, cycles, tophits, nreq, nacc;
+  int32_t err, pad;
+};
+
+template <class R>
+struct Birth {
+  int32_t sp, idx, k, cell;
+  uint64_t creator;
+  R off, v0, v1, v2;
+};
+
+template <class R>
+struct Request {
+  int32_t sp, chan, slot, cell;
+  uint64_t id;
+  R u_acc;
+  int32_t partner, acc;
+};
+
+template <class R>
+struct Store {
+  int32_t* cell;
+  R* off;
+  R* vx;
+  R* vy;
+  R* vz;
+  uint64_t* id;
+};
+
+template <class R>
+struct Dev {
+  Store<R> st[3];
+  Store<R> alt[3];
+  int64_t* N;       // [3] store lengths (including dead slots until the next sort)
+  int64_t* Nnew;    // [3]
+  int64_t cap[3];
+  int32_t* cnt;     // [3][Nc]    particles per cell
+  int64_t* F;       // [3][Nc]    sum of the 24-bit fractional positions per cell
+  int32_t* seg;     // [3][Nc+1]  cell segments of the last sort
+  int32_t* cursor;  // [3][Nc]
+  int32_t* segmax;  // [3]
+  R* E2;            // [Nc][2]    (E_c, E_c+1)
+  double* phi;      // [Nc+1]
+  double* E;        // [Nc+1]
+  const double* U;  // [M]
+  const R* sig;     // [NPT][TS]
+  Birth<R>* nb;
+  int32_t nb_cap, req_cap;
+  int32_t* nbc;     // [4] total, per species
+  Request<R>* req;
+  int32_t* nreq;
+  Counters* ctr;
+  int64_t* Qacc;
+  int64_t* Qlast;
+  double* phiacc;
+  double* philast;
+  int64_t* eedf_acc;
+  int64_t* eedf_last;
+  int64_t* fneg_acc;
+  int64_t* fneg_last;
+  uint32_t* done;   // [4] last-workgroup counters
+};
+
+// ---------------------------------------------------------------------------
+// random numbers: Philox4x32-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(x0, x1, x2, x3);
+}
+
+template <class R>
+__device__ __forceinline__ uint4 rng(const Consts<R>& C, uint64_t id, uint32_t n, uint32_t k) {
+  return philox((uint32_t)id, (uint32_t)(id >> 32), n, k, C.seed_lo, C.seed_hi);
+}
+
+template <class R> __device__ __forceinline__ R unif(uint32_t w);
+template <> __device__ __forceinline__ float unif<float>(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+template <> __device__ __forceinline__ double unif<double>(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+__device__ __forceinline__ double unif52(uint32_t a, uint32_t b) {
+  uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+  return ((double)m + 0.5) * 0x1p-52;
+}
+
+__device__ __forceinline__ float Sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double Sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float Floor(float x) { return floorf(x); }
+__device__ __forceinline__ double Floor(double x) { return floor(x); }
+
+// samplers: transcendentals in double, rounded once to R
+template <class R> __device__ __forceinline__ R bm_radius(R u) { return (R)sqrt(-2.0 * log((double)u)); }
+template <class R> __device__ __forceinline__ R cos2pi(R u) { return (R)cos(TWO_PI * (double)u); }
+template <class R> __device__ __forceinline__ R sin2pi(R u) { return (R)sin(TWO_PI * (double)u); }
+
+template <class R>
+__device__ __forceinline__ void iso_dir(uint32_t wc, uint32_t wp, R n[3]) {
+  R u = unif<R>(wc);
+  R ct = (R)1 - (R)2 * u;
+  R st = Sqrt((R)1 - ct * ct);
+  R up = unif<R>(wp);
+  n[0] = st * cos2pi<R>(up);
+  n[1] = st * sin2pi<R>(up);
+  n[2] = ct;
+}
+
+// ---------------------------------------------------------------------------
+// cross-section tables: binade grid, index and weight from the bits of E
+// ---------------------------------------------------------------------------
+template <class R>
+struct Lookup {
+  int k;
+  R t;
+  int mode;  // 0 inside, 1 below the first node, 2 at/above the last node
+};
+
+__device__ __forceinline__ Lookup<float> lookup(float E) {
+  uint32_t b = __float_as_uint(E);
+  if (b < 0x38800000u) return {0, 0.0f, 1};
+  if (b >= 0x46800000u) return {0, 0.0f, 2};
+  return {(int)((b >> 18) - (0x38800000u >> 18)), (float)(b & 0x3FFFFu) * 0x1p-18f, 0};
+}
+__device__ __forceinline__ Lookup<double> lookup(double E) {
+  uint64_t b = (uint64_t)__double_as_longlong(E);
+  if (b < 0x3F10000000000000ull) return {0, 0.0, 1};
+  if (b >= 0x40D0000000000000ull) return {0, 0.0, 2};
+  return {(int)((b >> 47) - (0x3F10000000000000ull >> 47)), (double)(b & ((1ull << 47) - 1)) * 0x1p-47, 0};
+}
+
+template <class R>
+__device__ __forceinline__ R sig_at(const R* tab, int j, const Lookup<R>& L) {
+  if (L.mode == 2) return tab[(NPT - 1) * TS + j];
+  R s0 = tab[L.k * TS + j];
+  if (L.mode == 1) return s0;
+  R s1 = tab[(L.k + 1) * TS + j];
+  R d = s1 - s0;
+  R p = L.t * d;
+  return s0 + p;
+}
+
+// ---------------------------------------------------------------------------
+// 128-bit integer to double, round to nearest even
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double u64_to_double_rn(uint64_t u) {
+  // both halves convert exactly, the product by 2^32 is exact, the sum rounds once
+  return (double)(uint32_t)(u >> 32) * 4294967296.0 + (double)(uint32_t)u;
+}
+
+__device__ inline double i128_to_double(__int128 x) {
+  bool neg = x < 0;
+  unsigned __int128 u = neg ? (unsigned __int128)(-x) : (unsigned __int128)x;
+  uint64_t hi = (uint64_t)(u >> 64);
+  double d;
+  if (hi == 0) {
+    d = u64_to_double_rn((uint64_t)u);
+  } else {
+    int p = 127 - __clzll(hi);  // position of the leading one, >= 64
+    int sh = p - 63;
+    uint64_t t = (uint64_t)(u >> sh);
+    unsigned __int128 rest = u & (((unsigned __int128)1 << sh) - 1);
+    if (rest != 0) t |= 1;  // sticky bit far below the rounding position
+    d = ldexp(u64_to_double_rn(t), sh);
+  }
+  return neg ? -d : d;
+}
+
+// ---------------------------------------------------------------------------
+// helpers shared by the kernels
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ int32_t frac24(R off) {
+  return (int32_t)(off * (R)16777216);
+}
+
+template <class R>
+__device__ __forceinline__ void deposit_global(const Dev<R>& D, int N, int sp, int cell, R off, int sign) {
+  int32_t f = frac24(off);
+  atomicAdd(&D.cnt[(size_t)sp * N + cell], sign);
+  atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)(int64_t)(sign * (int64_t)f));
+}
+
+template <class R>
+__device__ void add_birth(const Consts<R>& C, const Dev<R>& D, int sp, uint64_t creator, int k, int cell, R off,
+                          R v0, R v1, R v2) {
+  int b = atomicAdd(&D.nbc[0], 1);
+  int bs = atomicAdd(&D.nbc[1 + sp], 1);
+  if (b >= D.nb_cap || D.N[sp] + bs >= D.cap[sp]) {
+    atomicOr(&D.ctr->err, ERR_NB);
+    if (b < D.nb_cap) D.nb[b].sp = -1;
+    return;
+  }
+  Birth<R> r;
+  r.sp = sp;
+  r.idx = bs;
+  r.k = k;
+  r.cell = cell;
+  r.creator = creator;
+  r.off = off;
+  r.v0 = v0;
+  r.v1 = v1;
+  r.v2 = v2;
+  D.nb[b] = r;
+  deposit_global(D, C.N, sp, cell, off, 1);
+}
+
+template <class R>
+__device__ __forceinline__ uint64_t pick_key(const Consts<R>& C, uint64_t id_p, uint64_t id_t, uint32_t n) {
+  uint4 w = philox((uint32_t)id_p, (uint32_t)(id_p >> 32), (uint32_t)id_t, (uint32_t)(id_t >> 32), C.seed_lo ^ n,
+                   C.seed_hi ^ 0x5BD1E995u);
+  return ((uint64_t)(w.x >> 8) << 40) | (id_p & ID_MASK);
+}
+
+// equal-mass isotropic elastic collision of two electrons
+template <class R>
+__device__ __forceinline__ void ee_elastic(R va[3], R vb[3], const R n[3]) {
+  R V[3], g[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    V[d] = (va[d] + vb[d]) * (R)0.5;
+    g[d] = va[d] - vb[d];
+  }
+  R g2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+  R h = (R)0.5 * Sqrt(g2);
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    va[d] = V[d] + h * n[d];
+    vb[d] = V[d] - h * n[d];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// field: node charge from (count, fraction sum), exact Green's function of
+// the 3-point Dirichlet problem, boundary field from Gauss on a half cell
+// ---------------------------------------------------------------------------
+constexpr int FIELD_TPB = 1024;
+constexpr int NMAX_CELLS = 8192;
+
+// mode 0: solve only (creation); mode 1: step (diagnostics, clear the
+// accumulators of the species moved in this step)
+template <class R>
+__global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
+  __shared__ double phis[NMAX_CELLS + 1];
+  __shared__ __int128 scA[FIELD_TPB];
+  __shared__ __int128 scB[FIELD_TPB];
+  const int tid = threadIdx.x;
+  const int N = C.N;
+  const int64_t n = D.ctr->step;
+  const double U = D.U[n % C.M];
+  const bool ion = (n % C.nsub) == 0;
+  const int per = (N + 1 + FIELD_TPB - 1) / FIELD_TPB;
+  const int i0 = tid * per;
+  const int i1 = min(i0 + per, N + 1);
+  int64_t qloc[(NMAX_CELLS + FIELD_TPB) / FIELD_TPB];
+  __int128 a = 0, b = 0;
+  for (int i = i0; i < i1; i++) {
+    int64_t Qs[3];
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+      int64_t v = 0;
+      if (i < N) v += ((int64_t)D.cnt[s * N + i] << 24) - D.F[s * N + i];
+      if (i >= 1) v += D.F[s * N + i - 1];
+      Qs[s] = v;
+      if (mode == 1) D.Qacc[s * (N + 1) + i] += v;
+    }
+    int64_t q = (Qs[2] - Qs[0]) - Qs[1];
+    qloc[i - i0] = q;
+    if (i >= 1 && i <= N - 1) {
+      a += (__int128)i * q;
+      b += (__int128)(N - i) * q;
+    }
+  }
+  scA[tid] = a;
+  scB[tid] = b;
+  __syncthreads();
+  for (int d = 1; d < FIELD_TPB; d <<= 1) {
+    __int128 xa = 0, xb = 0;
+    if (tid >= d) {
+      xa = scA[tid - d];
+      xb = scB[tid - d];
+    }
+    __syncthreads();
+    scA[tid] += xa;
+    scB[tid] += xb;
+    __syncthreads();
+  }
+  __int128 S1 = scA[tid] - a;   // sum_{j < i0} j q_j
+  __int128 PB = scB[tid] - b;   // sum_{j < i0} (N-j) q_j
+  const __int128 TB = scB[FIELD_TPB - 1];
+  for (int i = i0; i < i1; i++) {
+    int64_t q = qloc[i - i0];
+    if (i >= 1 && i <= N - 1) {
+      S1 += (__int128)i * q;
+      PB += (__int128)(N - i) * q;
+    }
+    double ph;
+    if (i == 0) ph = U;
+    else if (i == N) ph = 0.0;
+    else {
+      __int128 S2 = TB - PB;  // sum_{j > i} (N-j) q_j
+      __int128 T = (__int128)(N - i) * S1 + (__int128)i * S2;
+      double x = U * (double)(N - i);
+      double y = C.cphi * i128_to_double(T);
+      ph = (x + y) / (double)N;
+    }
+    phis[i] = ph;
+  }
+  __syncthreads();
+  for (int i = i0; i < i1; i++) {
+    double e;
+    if (i == 0) e = (phis[0] - phis[1]) * C.invdx - C.cE * (double)qloc[0];
+    else if (i == N) e = (phis[N - 1] - phis[N]) * C.invdx + C.cE * (double)qloc[i - i0];
+    else e = (phis[i - 1] - phis[i + 1]) * C.inv2dx;
+    D.E[i] = e;
+    D.phi[i] = phis[i];
+    R er = (R)e;
+    if (i < N) D.E2[2 * i] = er;
+    if (i >= 1) D.E2[2 * (i - 1) + 1] = er;
+    if (mode == 1) D.phiacc[i] += phis[i];
+  }
+  if (mode == 1) {
+    // the passes of this step deposit every moved particle afresh
+    for (int s = 0; s < 3; s++) {
+      if (s != 0 && !ion) continue;
+      for (int i = tid; i < N; i += FIELD_TPB) {
+        D.cnt[s * N + i] = 0;
+        D.F[s * N + i] = 0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused push + null-collision MCC + deposit
+// ---------------------------------------------------------------------------
+template <class R>
+struct QEntry {
+  int32_t slot, cell;
+  R off, vx;
+};
+
+template <class R>
+struct PushLds {
+  uint64_t win[WIN];
+  QEntry<R> q[TILE];
+  int32_t eedf[EEDF_MAX + 1];
+  int32_t fneg[FNEG_MAX];
+  int32_t ev[NCH];
+  int32_t absorbed[6];
+  int32_t tophits;
+  int32_t qn;
+  int32_t base;
+  int32_t psteps;
+};
+
+template <class R, int S>
+__device__ __forceinline__ void diag_alive(const Consts<R>& C, PushLds<R>& L, int cell, R vx, R vy, R vz) {
+  if (S == 0) {
+    if (cell == C.cmid && C.eedf_bins > 0) {
+      R e2 = (vx * vx + vy * vy) + vz * vz;
+      R Ek = C.hme * e2;
+      R bf = Ek * C.eedf_sc;
+      int bin = (bf >= (R)C.eedf_bins) ? C.eedf_bins : (int)bf;
+      atomicAdd(&L.eedf[bin], 1);
+    }
+  } else if (S == 1) {
+    if (C.fneg_xbins > 0 && C.fneg_ebins > 0) {
+      R Ex = C.hmn * (vx * vx);
+      if (vx < (R)0) Ex = -Ex;
+      R bf = (Ex + C.fneg_em) * C.fneg_sc;
+      int eb = bf < (R)0 ? 0 : (bf >= (R)C.fneg_ebins ? C.fneg_ebins - 1 : (int)bf);
+      int xb = (int)(((int64_t)cell * C.fneg_xbins) / C.N);
+      atomicAdd(&L.fneg[xb * C.fneg_ebins + eb], 1);
+    }
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void deposit_win(PushLds<R>& L, const Dev<R>& D, int N, int sp, int base, int cell,
+                                            R off) {
+  int32_t f = frac24(off);
+  int idx = cell - base;
+  if ((unsigned)idx < (unsigned)WIN) {
+    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)((1ull << 40) + (uint64_t)f));
+  } else {
+    atomicAdd(&D.cnt[(size_t)sp * N + cell], 1);
+    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)f);
+  }
+}
+
+// collision with a gas molecule; returns false when the test particle is removed
+template <class R, int S>
+__device__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int slot, int cell, R off, uint64_t id,
+                          R v[3], const R vt[3], R g, R Erel, uint32_t n) {
+  uint4 w = rng(C, id, n, 2);
+  R n1[3], n2[3];
+  iso_dir<R>(w.x, w.y, n1);
+  iso_dir<R>(w.z, w.w, n2);
+  const R a = C.a_g[S], b = C.b_g[S];
+  R vc[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) vc[d] = b * v[d] + a * vt[d];
+  if (S == 0 && j == 10) {  // (15) dissociative attachment: O- born at v_cm
+    add_birth(C, D, 1, id, 0, cell, off, vc[0], vc[1], vc[2]);
+    return false;
+  }
+  if (S == 1 && (j == 15 || j == 16)) {  // (16) direct / (17) associative detachment
+    R f = (j == 15) ? C.ddf : C.adf;
+    R sp = f * g;
+    add_birth(C, D, 0, id, 0, cell, off, vc[0] + sp * n1[0], vc[1] + sp * n1[1], vc[2] + sp * n1[2]);
+    return false;
+  }
+  R gp = g;
+  if (C.loss[j] > (R)0) {
+    R Ep = Erel - C.loss[j];
+    gp = Sqrt(Ep * C.c2e_g[S]);
+  }
+  const R ag = a * gp, bg = b * gp;
+  if (S == 0 && j == 11) {  // (18) impact ionisation
+    R ve[3], vo[3], vn[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      ve[d] = vc[d] + ag * n1[d];
+      vo[d] = vc[d] - bg * n1[d];
+      vn[d] = vo[d];
+    }
+    ee_elastic<R>(ve, vn, n2);
+    v[0] = ve[0];
+    v[1] = ve[1];
+    v[2] = ve[2];
+    add_birth(C, D, 0, id, 0, cell, off, vn[0], vn[1], vn[2]);
+    add_birth(C, D, 2, id, 1, cell, off, vo[0], vo[1], vo[2]);
+    return true;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; d++) v[d] = vc[d] + ag * n1[d];
+  return true;
+}
+
+template <class R, int S>
+__device__ void candidate(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, const QEntry<R>& e, uint32_t n,
+                          int base) {
+  const Store<R> st = D.st[S];
+  const int N = C.N;
+  const int slot = e.slot, cell = e.cell;
+  const R off = e.off;
+  R v[3] = {e.vx, st.vy[slot], st.vz[slot]};
+  const uint64_t id = st.id[slot];
+  uint4 w = rng(C, id, n, 0);
+  const double U = unif52(w.x, w.y);
+  double cum = 0.0;
+  // partner channels first: slot size tau n_t(c) M_j (thinned later)
+  constexpr int NP = (S == 0) ? 2 : (S == 1 ? 1 : 0);
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    const int pi = (S == 0) ? q : 2;             // index into the partner-channel constants
+    const int chan = (S == 0) ? 12 + q : 17;
+    const int t = (chan == 13) ? 1 : 2;
+    const int32_t Lc = D.seg[t * (N + 1) + cell + 1] - D.seg[t * (N + 1) + cell];
+    cum = cum + (double)Lc * C.KP[pi];
+    if (U < cum) {
+      int r = atomicAdd(D.nreq, 1);
+      if (r < D.req_cap) {
+        Request<R> rq;
+        rq.sp = S;
+        rq.chan = chan;
+        rq.slot = slot;
+        rq.cell = cell;
+        rq.id = id;
+        rq.u_acc = unif<R>(w.z);
+        rq.partner = -1;
+        rq.acc = 0;
+        D.req[r] = rq;
+      } else {
+        atomicOr(&D.ctr->err, ERR_REQ);
+      }
+      deposit_win(L, D, N, S, base, cell, off);
+      diag_alive<R, S>(C, L, cell, v[0], v[1], v[2]);
+      return;
+    }
+  }
+  // gas target drawn from the Maxwellian at T_gas
+  uint4 u = rng(C, id, n, 1);
+  R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
+  R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
+  R vt[3];
+  vt[0] = C.vthg * (r1 * cos2pi<R>(a1));
+  vt[1] = C.vthg * (r1 * sin2pi<R>(a1));
+  vt[2] = C.vthg * (r2 * cos2pi<R>(a2));
+  R gx = v[0] - vt[0], gy = v[1] - vt[1], gz = v[2] - vt[2];
+  R g2 = (gx * gx + gy * gy) + gz * gz;
+  R g = Sqrt(g2);
+  R Erel = C.hmu_g[S] * g2;
+  if (Erel >= (R)16384) atomicAdd(&L.tophits, 1);
+  const Lookup<R> Lk = lookup(Erel);
+  constexpr int G0 = (S == 0) ? 0 : (S == 1 ? 14 : 18);
+  constexpr int NG = (S == 0) ? 12 : (S == 1 ? 3 : 1);
+  int hit = -1;
+#pragma unroll
+  for (int q = 0; q < NG; q++) {
+    const int j = G0 + q;
+    R sg = 0;
+    if (Erel >= C.thr[j]) sg = sig_at(D.sig, j, Lk) * g;
+    cum = cum + C.PG[j] * (double)sg;
+    if (hit < 0 && U < cum) hit = j;
+  }
+  bool alive = true;
+  if (hit >= 0) {
+    atomicAdd(&L.ev[hit], 1);
+    alive = gas_event<R, S>(C, D, hit, slot, cell, off, id, v, vt, g, Erel, n);
+    if (alive) {
+      st.vx[slot] = v[0];
+      st.vy[slot] = v[1];
+      st.vz[slot] = v[2];
+    } else {
+      st.cell[slot] = DEAD;
+    }
+  }
+  if (alive) {
+    deposit_win(L, D, N, S, base, cell, off);
+    diag_alive<R, S>(C, L, cell, v[0], v[1], v[2]);
+  }
+}
+
+template <class R> struct Vec4;
+template <> struct Vec4<float> {
+  static __device__ __forceinline__ void load(const float* p, float o[4]) {
+    float4 v = *(const float4*)p;
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+  static __device__ __forceinline__ void store(float* p, const float o[4]) {
+    *(float4*)p = make_float4(o[0], o[1], o[2], o[3]);
+  }
+};
+template <> struct Vec4<double> {
+  static __device__ __forceinline__ void load(const double* p, double o[4]) {
+    double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+  static __device__ __forceinline__ void store(double* p, const double o[4]) {
+    *(double2*)p = make_double2(o[0], o[1]);
+    *(double2*)(p + 2) = make_double2(o[2], o[3]);
+  }
+};
+
+template <class R, int S>
+__device__ void push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int64_t t0, int64_t Ns, uint32_t n,
+                          uint64_t T0, double pmax, int* my_abs, int* my_ps) {
+  const int tid = threadIdx.x;
+  const int N = C.N;
+  const Store<R> st = D.st[S];
+  if (tid == 0) {
+    int32_t c0 = st.cell[t0];
+    L.base = (c0 == DEAD ? 0 : c0) - 64;
+    L.qn = 0;
+  }
+  for (int i = tid; i < WIN; i += TPB) L.win[i] = 0;
+  __syncthreads();
+  const int base = L.base;
+  const int64_t s0 = t0 + (int64_t)PPT * tid;
+  int32_t c[4];
+  R off[4], vx[4];
+  uint64_t id[4];
+  const bool full = s0 + 3 < Ns;
+  if (full) {
+    int4 cv = *(const int4*)(st.cell + s0);
+    c[0] = cv.x; c[1] = cv.y; c[2] = cv.z; c[3] = cv.w;
+    Vec4<R>::load(st.off + s0, off);
+    Vec4<R>::load(st.vx + s0, vx);
+    ulonglong2 ia = *(const ulonglong2*)(st.id + s0), ib = *(const ulonglong2*)(st.id + s0 + 2);
+    id[0] = ia.x; id[1] = ia.y; id[2] = ib.x; id[3] = ib.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (s0 + q < Ns) {
+        c[q] = st.cell[s0 + q];
+        off[q] = st.off[s0 + q];
+        vx[q] = st.vx[s0 + q];
+        id[q] = st.id[s0 + q];
+      } else {
+        c[q] = DEAD;
+        off[q] = 0;
+        vx[q] = 0;
+        id[q] = 0;
+      }
+    }
+  }
+  const bool was_dead[4] = {c[0] == DEAD, c[1] == DEAD, c[2] == DEAD, c[3] == DEAD};
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (was_dead[q]) continue;
+    (*my_ps)++;
+    const R E0 = D.E2[2 * c[q]], E1 = D.E2[2 * c[q] + 1];
+    const R dE = E1 - E0;
+    const R tt = off[q] * dE;
+    const R Ep = E0 + tt;
+    const R dv = C.qmdt[S] * Ep;
+    vx[q] = vx[q] + dv;
+    const R dxp = vx[q] * C.dtdx[S];
+    R o = off[q] + dxp;
+    const R fl = Floor(o);
+    if (!(fl == fl) || fl > (R)1e9 || fl < (R)-1e9) {
+      c[q] = DEAD;
+      atomicOr(&D.ctr->err, ERR_NAN);
+      continue;
+    }
+    int32_t cn = c[q] + (int32_t)fl;
+    o = o - fl;
+    if (o >= (R)1) {
+      o = 0;
+      cn += 1;
+    }
+    off[q] = o;
+    if (cn < 0) {
+      c[q] = DEAD;
+      my_abs[0]++;
+      continue;
+    }
+    if (cn >= N) {
+      c[q] = DEAD;
+      my_abs[1]++;
+      continue;
+    }
+    c[q] = cn;
+    const uint4 w = rng(C, id[q], n, 0);
+    if ((uint64_t)w.x < T0 && unif52(w.x, w.y) < pmax) {
+      int qi = atomicAdd(&L.qn, 1);
+      QEntry<R> e;
+      e.slot = (int32_t)(s0 + q);
+      e.cell = cn;
+      e.off = o;
+      e.vx = vx[q];
+      L.q[qi] = e;
+    } else {
+      deposit_win(L, D, N, S, base, cn, o);
+      if (S == 0) {
+        if (cn == C.cmid) diag_alive<R, S>(C, L, cn, vx[q], st.vy[s0 + q], st.vz[s0 + q]);
+      } else if (S == 1) {
+        diag_alive<R, S>(C, L, cn, vx[q], (R)0, (R)0);
+      }
+    }
+  }
+  if (full) {
+    *(int4*)(st.cell + s0) = make_int4(c[0], c[1], c[2], c[3]);
+    Vec4<R>::store(st.off + s0, off);
+    Vec4<R>::store(st.vx + s0, vx);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (s0 + q < Ns && !was_dead[q]) {
+        st.cell[s0 + q] = c[q];
+        st.off[s0 + q] = off[q];
+        st.vx[s0 + q] = vx[q];
+      }
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int qn = L.qn;
+  for (int k = tid; k < qn; k += TPB) candidate<R, S>(C, D, L, L.q[k], n, base);
+  __syncthreads();
+  int32_t* cnt_s = D.cnt + (size_t)S * N;
+  int64_t* F_s = D.F + (size_t)S * N;
+  for (int i = tid; i < WIN; i += TPB) {
+    uint64_t v = L.win[i];
+    if (v) {
+      int cc = base + i;
+      atomicAdd(&cnt_s[cc], (int)(v >> 40));
+      atomicAdd((unsigned long long*)&F_s[cc], (unsigned long long)(v & F_MASK));
+    }
+  }
+  __syncthreads();
+}
+
+template <class R>
+__device__ __forceinline__ double pmax_of(const Consts<R>& C, const Dev<R>& D, int s) {
+  double P = C.PGtot[s];
+  if (s == 0) {
+    P = P + (double)D.segmax[2] * C.KP[0];
+    P = P + (double)D.segmax[1] * C.KP[1];
+  } else if (s == 1) {
+    P = P + (double)D.segmax[2] * C.KP[2];
+  }
+  return P;
+}
+
+template <class R>
+__global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
+  __shared__ PushLds<R> L;
+  const int tid = threadIdx.x;
+  const int64_t nstep = D.ctr->step;
+  const uint32_t n = (uint32_t)nstep;
+  const bool ion = (nstep % C.nsub) == 0;
+  for (int i = tid; i < EEDF_MAX + 1; i += TPB) L.eedf[i] = 0;
+  for (int i = tid; i < FNEG_MAX; i += TPB) L.fneg[i] = 0;
+  if (tid < NCH) L.ev[tid] = 0;
+  if (tid < 6) L.absorbed[tid] = 0;
+  if (tid == 0) {
+    L.tophits = 0;
+    L.psteps = 0;
+  }
+  __syncthreads();
+  int64_t Ns[3], nt[3];
+  double pm[3];
+  uint64_t T0[3];
+  for (int s = 0; s < 3; s++) {
+    Ns[s] = (s == 0 || ion) ? D.N[s] : 0;
+    nt[s] = (Ns[s] + TILE - 1) / TILE;
+    pm[s] = pmax_of(C, D, s);
+    double t = ceil(pm[s] * 4294967296.0);
+    T0[s] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+    if (Ns[s] > 0 && pm[s] > 1.0 && blockIdx.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
+  }
+  const int64_t total = nt[0] + nt[1] + nt[2];
+  int my_abs[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int my_ps = 0;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    if (t < nt[0]) push_tile<R, 0>(C, D, L, t * TILE, Ns[0], n, T0[0], pm[0], my_abs[0], &my_ps);
+    else if (t < nt[0] + nt[1]) push_tile<R, 1>(C, D, L, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1], my_abs[1], &my_ps);
+    else push_tile<R, 2>(C, D, L, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2], my_abs[2], &my_ps);
+  }
+  for (int sp = 0; sp < 3; sp++)
+    for (int side = 0; side < 2; side++)
+      if (my_abs[sp][side]) atomicAdd(&L.absorbed[side * 3 + sp], my_abs[sp][side]);
+  if (my_ps) atomicAdd(&L.psteps, my_ps);
+  __syncthreads();
+  if (tid < 6 && L.absorbed[tid]) atomicAdd((unsigned long long*)&D.ctr->absorbed[tid], (unsigned long long)L.absorbed[tid]);
+  if (tid == 0 && L.psteps) atomicAdd((unsigned long long*)&D.ctr->psteps, (unsigned long long)L.psteps);
+  if (tid < NCH && L.ev[tid]) atomicAdd((unsigned long long*)&D.ctr->events[tid], (unsigned long long)L.ev[tid]);
+  if (tid == 0 && L.tophits) atomicAdd((unsigned long long*)&D.ctr->tophits, (unsigned long long)L.tophits);
+  if (C.eedf_bins > 0)
+    for (int i = tid; i <= C.eedf_bins; i += TPB)
+      if (L.eedf[i]) atomicAdd((unsigned long long*)&D.eedf_acc[i], (unsigned long long)L.eedf[i]);
+  const int nf = C.fneg_xbins * C.fneg_ebins;
+  for (int i = tid; i < nf; i += TPB)
+    if (L.fneg[i]) atomicAdd((unsigned long long*)&D.fneg_acc[i], (unsigned long long)L.fneg[i]);
+}
+
+
+// ---------------------------------------------------------------------------
+// last-workgroup detection (no spinning: the final workgroup to arrive does
+// the serial part)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool last_block(uint32_t* counter) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// ---------------------------------------------------------------------------
+// partner reactions (13), (14), (19): partner pick in the cell segment of the
+// last sort, acceptance sigma g / M_j, claims (smallest test id wins; electron
+// requests before O- requests), kinematics, births and charge corrections
+// ---------------------------------------------------------------------------
+constexpr int CLAIM_TPB = 256;
+
+template <class R>
+__device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int slot) {
+  const Store<R> st = D.st[sp];
+  int cell = st.cell[slot];
+  if (cell == DEAD) return;
+  R off = st.off[slot];
+  deposit_global(D, C.N, sp, cell, off, -1);
+  st.cell[slot] = DEAD;
+}
+
+template <class R>
+__global__ void __launch_bounds__(CLAIM_TPB) k_claims(Consts<R> C, Dev<R> D) {
+  __shared__ uint64_t bk[CLAIM_TPB];
+  __shared__ int32_t bi[CLAIM_TPB];
+  __shared__ int32_t rpart[REQ_CAP];
+  __shared__ uint64_t rid[REQ_CAP];
+  __shared__ uint8_t racc[REQ_CAP];
+  __shared__ uint8_t rwin[REQ_CAP];
+  const int tid = threadIdx.x;
+  int nr = *D.nreq;
+  if (nr == 0) return;
+  if (nr > D.req_cap) nr = D.req_cap;
+  const int N = C.N;
+  const uint32_t n = (uint32_t)D.ctr->step;
+  for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+    const Request<R> q = D.req[r];
+    const int t = (q.chan == 13) ? 1 : 2;
+    const int32_t lo = D.seg[t * (N + 1) + q.cell], hi = D.seg[t * (N + 1) + q.cell + 1];
+    uint64_t best = ~0ull;
+    int32_t bslot = -1;
+    for (int32_t i = lo + tid; i < hi; i += CLAIM_TPB) {
+      uint64_t k = pick_key(C, D.st[t].id[i], q.id, n);
+      if (k < best) {
+        best = k;
+        bslot = i;
+      }
+    }
+    bk[tid] = best;
+    bi[tid] = bslot;
+    __syncthreads();
+    for (int d = CLAIM_TPB / 2; d > 0; d >>= 1) {
+      if (tid < d && bk[tid + d] < bk[tid]) {
+        bk[tid] = bk[tid + d];
+        bi[tid] = bi[tid + d];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      int32_t p = bi[0];
+      int acc = 0;
+      if (p >= 0 && D.st[t].cell[p] != DEAD) {
+        const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
+        const Store<R> ts = D.st[q.sp], ps = D.st[t];
+        R gx = ts.vx[q.slot] - ps.vx[p], gy = ts.vy[q.slot] - ps.vy[p], gz = ts.vz[q.slot] - ps.vz[p];
+        R g2 = (gx * gx + gy * gy) + gz * gz;
+        R g = Sqrt(g2);
+        R Erel = C.hmu_c[pi] * g2;
+        R sg = 0;
+        if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, q.chan, lookup(Erel)) * g;
+        acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
+      }
+      D.req[r].partner = p;
+      D.req[r].acc = acc;
+    }
+    __syncthreads();
+  }
+  if (!last_block(&D.done[0])) return;
+  if (tid == 0) D.done[0] = 0;
+  // ---- serial part, one workgroup ----
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    Request<R> q = D.req[r];
+    rpart[r] = q.partner;
+    rid[r] = q.id;
+    racc[r] = (uint8_t)q.acc;
+    rwin[r] = 0;
+  }
+  __syncthreads();
+  // stage 1: electron test particles, partner species differ by channel
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    const Request<R> q = D.req[r];
+    if (q.sp != 0 || !racc[r]) continue;
+    int win = 1;
+    for (int r2 = 0; r2 < nr && win; r2++) {
+      if (r2 == r || !racc[r2]) continue;
+      const int c2 = D.req[r2].chan;
+      if (c2 != q.chan) continue;  // (13) takes O2+, (19) takes O-
+      if (rpart[r2] == rpart[r] && rid[r2] < rid[r]) win = 0;
+    }
+    rwin[r] = (uint8_t)win;
+  }
+  __syncthreads();
+  int nacc = 0;
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    if (!rwin[r]) continue;
+    const Request<R> q = D.req[r];
+    nacc++;
+    atomicAdd((unsigned long long*)&D.ctr->events[q.chan], 1ull);
+    if (q.chan == 12) {
+      kill_particle(C, D, 0, q.slot);
+      kill_particle(C, D, 2, q.partner);
+      continue;
+    }
+    // (19): inelastic e-O- collision, O- split into O + e, e-e elastic
+    const Store<R> es = D.st[0], ns = D.st[1];
+    const int p = q.partner;
+    R T[3] = {es.vx[q.slot], es.vy[q.slot], es.vz[q.slot]};
+    R P[3] = {ns.vx[p], ns.vy[p], ns.vz[p]};
+    const R a = C.a_c[1], b = C.b_c[1];
+    R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
+    R g2 = (gx * gx + gy * gy) + gz * gz;
+    R Erel = C.hmu_c[1] * g2;
+    uint4 w = rng(C, q.id, n, 2);
+    R n1[3], n2[3];
+    iso_dir<R>(w.x, w.y, n1);
+    iso_dir<R>(w.z, w.w, n2);
+    R Ep = Erel - C.loss[13];
+    R gp = Sqrt(Ep * C.c2e_c[1]);
+    R ag = a * gp, bg = b * gp;
+    R ve[3], vn[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      R vc = b * T[d] + a * P[d];
+      ve[d] = vc + ag * n1[d];
+      vn[d] = vc - bg * n1[d];
+    }
+    ee_elastic<R>(ve, vn, n2);
+    es.vx[q.slot] = ve[0];
+    es.vy[q.slot] = ve[1];
+    es.vz[q.slot] = ve[2];
+    const int pc = ns.cell[p];
+    const R po = ns.off[p];
+    kill_particle(C, D, 1, p);
+    add_birth(C, D, 0, q.id, 0, pc, po, vn[0], vn[1], vn[2]);
+  }
+  __syncthreads();
+  // stage 2: O- test particles (14); the O- must not have been taken by a
+  // (19) winner and the O2+ not by a (13) winner
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    const Request<R> q = D.req[r];
+    if (q.sp != 1 || !racc[r]) continue;
+    int ok = 1;
+    for (int r2 = 0; r2 < nr && ok; r2++) {
+      if (!rwin[r2]) continue;
+      const int c2 = D.req[r2].chan;
+      if (c2 == 13 && rpart[r2] == q.slot) ok = 0;
+      if (c2 == 12 && rpart[r2] == rpart[r]) ok = 0;
+    }
+    racc[r] = (uint8_t)(ok ? 2 : 0);
+  }
+  __syncthreads();
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    if (racc[r] != 2) continue;
+    int win = 1;
+    for (int r2 = 0; r2 < nr && win; r2++) {
+      if (r2 == r || racc[r2] != 2) continue;
+      if (rpart[r2] == rpart[r] && rid[r2] < rid[r]) win = 0;
+    }
+    rwin[r] = (uint8_t)(win ? 3 : 0);
+  }
+  __syncthreads();
+  for (int r = tid; r < nr; r += CLAIM_TPB) {
+    if (rwin[r] != 3) continue;
+    const Request<R> q = D.req[r];
+    nacc++;
+    atomicAdd((unsigned long long*)&D.ctr->events[17], 1ull);
+    kill_particle(C, D, 1, q.slot);
+    kill_particle(C, D, 2, q.partner);
+  }
+  if (nacc) atomicAdd((unsigned long long*)&D.ctr->nacc, (unsigned long long)nacc);
+  if (tid == 0) atomicAdd((unsigned long long*)&D.ctr->nreq, (unsigned long long)nr);
+}
+
+// ---------------------------------------------------------------------------
+// births: canonical ids (rank by creator id, then k), append to the stores;
+// the last workgroup closes the step
+// ---------------------------------------------------------------------------
+constexpr int BIRTH_TPB = 256;
+
+template <class R>
+__global__ void __launch_bounds__(BIRTH_TPB) k_births(Consts<R> C, Dev<R> D) {
+  __shared__ uint64_t keys[BIRTH_TPB];
+  const int tid = threadIdx.x;
+  int B = D.nbc[0];
+  if (B > D.nb_cap) B = D.nb_cap;
+  const uint64_t next = (uint64_t)D.ctr->next_id;
+  for (int b0 = blockIdx.x * BIRTH_TPB; b0 < B; b0 += gridDim.x * BIRTH_TPB) {
+    const int b = b0 + tid;
+    uint64_t key = ~0ull;
+    Birth<R> rec;
+    if (b < B) {
+      rec = D.nb[b];
+      key = (rec.creator << 1) | (uint64_t)rec.k;
+    }
+    int rank = 0;
+    for (int t0 = 0; t0 < B; t0 += BIRTH_TPB) {
+      keys[tid] = (t0 + tid < B) ? ((D.nb[t0 + tid].creator << 1) | (uint64_t)D.nb[t0 + tid].k) : ~0ull;
+      __syncthreads();
+      const int m = min(BIRTH_TPB, B - t0);
+      for (int i = 0; i < m; i++) rank += (keys[i] < key);
+      __syncthreads();
+    }
+    if (b < B && rec.sp >= 0) {
+      const int sp = rec.sp;
+      const int64_t slot = D.N[sp] + rec.idx;
+      if (slot < D.cap[sp]) {
+        const Store<R> st = D.st[sp];
+        st.cell[slot] = rec.cell;
+        st.off[slot] = rec.off;
+        st.vx[slot] = rec.v0;
+        st.vy[slot] = rec.v1;
+        st.vz[slot] = rec.v2;
+        st.id[slot] = next + (uint64_t)rank;
+      }
+    }
+  }
+  if (!last_block(&D.done[1])) return;
+  __shared__ int64_t new_step;
+  if (tid == 0) {
+    D.done[1] = 0;
+    for (int s = 0; s < 3; s++) {
+      int64_t nn = D.N[s] + D.nbc[1 + s];
+      if (nn > D.cap[s]) {
+        nn = D.cap[s];
+        atomicOr(&D.ctr->err, ERR_CAP);
+      }
+      D.N[s] = nn;
+      D.nbc[1 + s] = 0;
+    }
+    D.ctr->next_id += B;
+    D.ctr->births += B;
+    if ((uint64_t)D.ctr->next_id > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
+    D.nbc[0] = 0;
+    *D.nreq = 0;
+    D.ctr->step += 1;
+    new_step = D.ctr->step;
+  }
+  __syncthreads();
+  // close the rf cycle: move the accumulated sums to the last-cycle buffers
+  if (new_step % C.M == 0) {
+    const int N = C.N;
+    for (int i = tid; i < 3 * (N + 1); i += BIRTH_TPB) {
+      D.Qlast[i] = D.Qacc[i];
+      D.Qacc[i] = 0;
+    }
+    for (int i = tid; i <= N; i += BIRTH_TPB) {
+      D.philast[i] = D.phiacc[i];
+      D.phiacc[i] = 0;
+    }
+    for (int i = tid; i <= C.eedf_bins; i += BIRTH_TPB) {
+      D.eedf_last[i] = D.eedf_acc[i];
+      D.eedf_acc[i] = 0;
+    }
+    for (int i = tid; i < C.fneg_xbins * C.fneg_ebins; i += BIRTH_TPB) {
+      D.fneg_last[i] = D.fneg_acc[i];
+      D.fneg_acc[i] = 0;
+    }
+    if (tid == 0) D.ctr->cycles += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cell sort (counting sort by cell, dead particles dropped); the segments it
+// produces are the partner populations of the cells until the next sort
+// ---------------------------------------------------------------------------
+constexpr int SCAN_TPB = 1024;
+
+template <class R>
+__global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
+  __shared__ int64_t part[SCAN_TPB];
+  __shared__ int32_t pmax[SCAN_TPB];
+  const int s = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int N = C.N;
+  const int per = (N + SCAN_TPB - 1) / SCAN_TPB;
+  const int i0 = tid * per, i1 = min(i0 + per, N);
+  int64_t sum = 0;
+  int32_t mx = 0;
+  for (int i = i0; i < i1; i++) {
+    int32_t c = D.cnt[s * N + i];
+    sum += c;
+    mx = max(mx, c);
+  }
+  part[tid] = sum;
+  pmax[tid] = mx;
+  __syncthreads();
+  for (int d = 1; d < SCAN_TPB; d <<= 1) {
+    int64_t x = (tid >= d) ? part[tid - d] : 0;
+    int32_t y = (tid >= d) ? pmax[tid - d] : 0;
+    __syncthreads();
+    part[tid] += x;
+    pmax[tid] = max(pmax[tid], y);
+    __syncthreads();
+  }
+  int64_t run = part[tid] - sum;
+  for (int i = i0; i < i1; i++) {
+    D.seg[s * (N + 1) + i] = (int32_t)run;
+    D.cursor[s * N + i] = (int32_t)run;
+    run += D.cnt[s * N + i];
+  }
+  if (tid == SCAN_TPB - 1) {
+    D.seg[s * (N + 1) + N] = (int32_t)part[SCAN_TPB - 1];
+    D.Nnew[s] = part[SCAN_TPB - 1];
+    D.segmax[s] = pmax[SCAN_TPB - 1];
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_sort_scatter(Consts<R> C, Dev<R> D) {
+  const int N = C.N;
+  const int lane = threadIdx.x & 63;
+  int64_t Ns[3], tot = 0;
+  for (int s = 0; s < 3; s++) {
+    Ns[s] = D.N[s];
+    tot += Ns[s];
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform loop bound so that every lane takes part in the ballots
+  const int64_t span = ((tot + stride - 1) / stride) * stride;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < span; g += stride) {
+    int s = 0;
+    int64_t i = g;
+    bool valid = g < tot;
+    if (valid) {
+      if (i >= Ns[0]) {
+        i -= Ns[0];
+        s = 1;
+        if (i >= Ns[1]) {
+          i -= Ns[1];
+          s = 2;
+        }
+      }
+    }
+    int32_t cell = valid ? D.st[s].cell[i] : DEAD;
+    bool alive = valid && cell != DEAD;
+    // group the lanes of the wave by (species, cell); one atomic per group
+    const int key = alive ? (s * (N + 1) + cell) : -1;
+    uint64_t pending = __ballot(alive);
+    int32_t dst = -1;
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int lkey = __shfl(key, leader);
+      const uint64_t peers = __ballot(key == lkey);
+      const int cnt = __popcll(peers);
+      const int rank = __popcll(peers & ((1ull << lane) - 1));
+      int basei = 0;
+      if (lane == leader) {
+        const int ls = lkey / (N + 1), lc = lkey % (N + 1);
+        basei = atomicAdd(&D.cursor[ls * N + lc], cnt);
+      }
+      basei = __shfl(basei, leader);
+      if (key == lkey) dst = basei + rank;
+      pending &= ~peers;
+    }
+    if (alive) {
+      const int32_t lim = D.seg[s * (N + 1) + cell + 1];
+      if (dst < 0 || dst >= lim) {
+        atomicOr(&D.ctr->err, ERR_SORT);
+      } else {
+        const Store<R> a = D.st[s], b = D.alt[s];
+        b.cell[dst] = cell;
+        b.off[dst] = a.off[i];
+        b.vx[dst] = a.vx[i];
+        b.vy[dst] = a.vy[i];
+        b.vz[dst] = a.vz[i];
+        b.id[dst] = a.id[i];
+      }
+    }
+  }
+  if (!last_block(&D.done[2])) return;
+  if (threadIdx.x == 0) {
+    D.done[2] = 0;
+    for (int s = 0; s < 3; s++) D.N[s] = D.Nnew[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// creation: initial load, charge deposit, leapfrog half step back
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void k_load(Consts<R> C, Dev<R> D, int64_t n_e, int64_t n_n, int64_t n_p) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = n_e + n_n + n_p;
+  if (id >= tot) return;
+  int s = 0;
+  int64_t i = id;
+  if (i >= n_e) {
+    i -= n_e;
+    s = 1;
+    if (i >= n_n) {
+      i -= n_n;
+      s = 2;
+    }
+  }
+  uint4 w = rng(C, (uint64_t)id, 0xFFFFFFFFu, 0);
+  uint4 u = rng(C, (uint64_t)id, 0xFFFFFFFFu, 1);
+  const Store<R> st = D.st[s];
+  st.id[i] = (uint64_t)id;
+  st.cell[i] = (int32_t)(((uint64_t)w.x * (uint64_t)C.N) >> 32);
+  st.off[i] = unif<R>(w.y);
+  R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
+  R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
+  st.vx[i] = C.vth0[s] * (r1 * cos2pi<R>(a1));
+  st.vy[i] = C.vth0[s] * (r1 * sin2pi<R>(a1));
+  st.vz[i] = C.vth0[s] * (r2 * cos2pi<R>(a2));
+}
+
+template <class R>
+__global__ void k_deposit_all(Consts<R> C, Dev<R> D) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = g;
+  int s = 0;
+  while (s < 3 && i >= D.N[s]) {
+    i -= D.N[s];
+    s++;
+  }
+  if (s >= 3) return;
+  const int32_t cell = D.st[s].cell[i];
+  if (cell == DEAD) return;
+  deposit_global(D, C.N, s, cell, D.st[s].off[i], 1);
+}
+
+template <class R>
+__global__ void k_halfkick(Consts<R> C, Dev<R> D) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = g;
+  int s = 0;
+  while (s < 3 && i >= D.N[s]) {
+    i -= D.N[s];
+    s++;
+  }
+  if (s >= 3) return;
+  const Store<R> st = D.st[s];
+  const int32_t c = st.cell[i];
+  if (c == DEAD) return;
+  const R E0 = D.E2[2 * c], E1 = D.E2[2 * c + 1];
+  const R dE = E1 - E0;
+  const R tt = st.off[i] * dE;
+  const R Ep = E0 + tt;
+  const R dv = C.hk[s] * Ep;
+  st.vx[i] = st.vx[i] - dv;
+}
+
+}  // namespace pic

@@ -1,0 +1,175 @@
+"""GPU (HIP, gfx950) against the CPU oracle, step by step.
+
+Both sides draw the same Philox streams and follow the same operation order,
+so particle ids, cells, counts, collision events and the integer node charge
+must agree exactly; positions and velocities must agree to 1e-5 relative in
+FP32 (the bar of the method's precision statement) and 1e-12 in FP64.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from pic_inputs import build_tables, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": (1e-5, 1e-6), "fp64": (1e-12, 1e-12)}
+
+
+def _gpu():
+    from paper_0705_0495_amd import Discharge
+    return Discharge
+
+
+def _by_id(t):
+    ids, cell, off, v = t
+    a = np.argsort(ids, kind="stable")
+    return ids[a], cell[a], off[a], v[a]
+
+
+def compare(g, o, prec, label, sample_mod=None):
+    rtol, otol = TOL[prec]
+    for s in range(3):
+        gi, gc, go, gv = _by_id(g.particles(s))
+        oi, oc, oo, ov = _by_id(o.particles(s))
+        assert len(gi) == len(oi), f"{label} species {s}: {len(gi)} vs {len(oi)} particles"
+        if sample_mod:
+            kg, ko = gi % sample_mod == 0, oi % sample_mod == 0
+            gi, gc, go, gv = gi[kg], gc[kg], go[kg], gv[kg]
+            oi, oc, oo, ov = oi[ko], oc[ko], oo[ko], ov[ko]
+        assert np.array_equal(gi, oi), f"{label} species {s}: ids differ"
+        bad = np.nonzero(gc != oc)[0]
+        assert len(bad) == 0, f"{label} species {s}: {len(bad)} cells differ, first id {gi[bad[0]]}"
+        assert np.allclose(go, oo, rtol=0, atol=otol), f"{label} species {s}: positions"
+        scale = np.maximum(np.abs(ov), np.abs(ov).max(axis=0, keepdims=True) * 1e-3)
+        err = np.abs(gv - ov) / np.maximum(scale, 1e-30)
+        assert err.max() <= rtol, f"{label} species {s}: velocity rel err {err.max()}"
+    m = g.moments()
+    ev, ab, misc = o.counters()
+    assert np.array_equal(m["events"], ev), f"{label}: events {m['events']} vs {ev}"
+    assert np.array_equal(m["absorbed"], ab), f"{label}: absorbed {m['absorbed']} vs {ab}"
+    assert m["step"] == misc["step"] and m["next_id"] == misc["next_id"] and m["births"] == misc["births"]
+    assert m["particle_steps"] == misc["psteps"]
+    assert np.array_equal(g.charge(), o.charge()), f"{label}: node charge differs"
+
+
+def ragged_small(**kw):
+    return dataclasses.replace(workload("small"), n_init=(5003, 1001, 4999), **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_creation_matches_oracle(prec):
+    wl = ragged_small()
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    compare(g, o, prec, "creation")
+    gphi, gE = g.field()
+    ophi, oE = o.field()
+    assert np.array_equal(gphi, ophi)
+    assert np.array_equal(gE, oE)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("boost", [1.0, 3e6])
+def test_steps_match_oracle(prec, boost):
+    wl = ragged_small()
+    sig, thr, loss = build_tables(partner_boost=boost)
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    done = 0
+    for target in (1, 2, 5, 11, 30, 80, 200):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        g.sync()
+        compare(g, o, prec, f"step {done}")
+        gphi, gE = g.field()
+        ophi, oE = o.field()
+        assert np.array_equal(gphi, ophi), f"step {done}: potential differs"
+    if boost > 1:
+        ev, _, misc = o.counters()
+        assert ev[12] + ev[13] + ev[17] > 0 and misc["requests"] > 0
+
+
+def test_subcycled_ions_match_oracle():
+    wl = ragged_small(ion_subcycle=3, sort_every=6)
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    for k in range(4):
+        g.step(25)
+        o.step(25)
+        compare(g, o, "fp32", f"subcycled step {25 * (k + 1)}")
+
+
+def test_one_rf_cycle_diagnostics_match_oracle():
+    wl = workload("small")
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(wl.steps_per_period)
+    o.step(wl.steps_per_period)
+    compare(g, o, "fp32", "one cycle")
+    m = g.moments()
+    Q, phi, eedf, fneg = o.cycle_sums()
+    assert m["cycles"] == 1
+    assert np.array_equal(m["eedf"], eedf)
+    assert np.array_equal(m["fneg"], fneg)
+    dx = wl.gap_m / wl.n_cells
+    vol = np.full(wl.n_cells + 1, wl.area_m2 * dx)
+    vol[0] *= 0.5
+    vol[-1] *= 0.5
+    dens = wl.weight * (Q / 16777216.0) / vol / wl.steps_per_period
+    assert np.allclose(m["density"], dens, rtol=1e-14, atol=0)
+    assert np.array_equal(m["phi"], phi / wl.steps_per_period)
+
+
+def test_results_independent_of_launch_shape():
+    wl = ragged_small()
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    ref = None
+    for grid in (0, 1, 7, 61):
+        g = _gpu()(wl, sig, thr, loss, precision="fp32")
+        if grid:
+            g.set_grid(grid)
+        g.step(60)
+        out = [_by_id(g.particles(s)) for s in range(3)]
+        ev = g.moments()["events"]
+        if ref is None:
+            ref = (out, ev)
+            continue
+        for s in range(3):
+            for a, b in zip(out[s], ref[0][s]):
+                assert np.array_equal(a, b)
+        assert np.array_equal(ev, ref[1])
+        g.close()
+
+
+def test_production_size_matches_oracle():
+    """The 4.5M-particle production discharge, a few steps, in the launch
+    configuration the benchmark uses."""
+    wl = workload("prod")
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    for target in (1, 11):
+        g.step(target - (0 if target == 1 else 1))
+        o.step(target - (0 if target == 1 else 1))
+        compare(g, o, "fp32", f"prod step {target}")
+
+
+def test_large_size_matches_oracle_sampled():
+    """The 2^25-particle discharge: one step, counters and charge in full, every
+    997th particle compared one by one."""
+    wl = workload("large")
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    o.step(1)
+    compare(g, o, "fp32", "large step 1", sample_mod=997)
