@@ -1,0 +1,152 @@
+"""Throughput of the PIC-MCC particle step on one MI355X.
+
+Workload (default): the large single discharge -- 6 cm gap, 4096 cells, O2 at
+100 Pa / 300 K, 400 V at 13.56 MHz, dt = T_rf/8000, 2^25 macro particles
+(50 % e, 10 % O-, 40 % O2+), FP32 particle state, 24-bit fixed-point charge,
+FP64 field solve.  A step is one pass of the whole hot path: field solve,
+fused gather/push/absorb/null-collision MCC/deposit of every species, partner
+reactions, births, and every 10th step the cell sort.
+
+Prints one JSON line.  ``value`` is particle pushes per second over the timed
+steps (inputs resident in HBM, wall clock between two stream synchronisations).
+``roofline`` prices the fused particle kernel against HBM: algorithmic bytes
+per particle push (FP32) = read cell 4 + off 4 + vx 4 + id 8, write cell 4 +
+off 4 + vx 4 = 32 B, divided by the kernel's average duration from HIP events
+recorded on the library's stream around every launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PUSH = {"fp32": 32, "fp64": 56}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_push.json")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40000)
+    ap.add_argument("--warmup", type=int, default=8000)
+    ap.add_argument("--workload", default="large", choices=["small", "prod", "large"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--cpu-scale", type=float, default=1.0 / 32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the discharge is not sharded "
+              "across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_0705_0495_amd import Discharge
+    from pic_inputs import build_tables, workload
+
+    wl = workload(args.workload)
+    sig, thr, loss = build_tables()
+    t0 = time.time()
+    cap = [4 * n + (1 << 20) for n in wl.n_init]
+    d = Discharge(wl, sig, thr, loss, precision=args.precision, capacity=cap)
+    print(f"[bench] created {args.workload} ({sum(wl.n_init)} particles) in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    done = 0
+    chunk = 500
+    while done < args.warmup:
+        k = min(chunk, args.warmup - done)
+        tw = time.perf_counter()
+        d.step(k)
+        d.sync()
+        done += k
+        m = d.moments()
+        print(f"[bench] warmup {done}/{args.warmup}: {(time.perf_counter() - tw) * 1e3 / k:.3f} ms/step, "
+              f"alive {m['alive']}", file=sys.stderr, flush=True)
+    m0 = d.moments()
+    d.timing(True)
+    d.sync()
+    t0 = time.perf_counter()
+    done = 0
+    report = 4000
+    while done < args.steps:
+        k = min(report, args.steps - done)
+        d.step(k)
+        done += k
+        if done < args.steps:
+            d.sync()
+            print(f"[bench] timed {done}/{args.steps}", file=sys.stderr, flush=True)
+    d.sync()
+    elapsed = time.perf_counter() - t0
+    push_ms, launches = d.kernel_time()
+    d.timing(False)
+    m1 = d.moments()
+    psteps = m1["particle_steps"] - m0["particle_steps"]
+    value = psteps / elapsed
+    print(f"[bench] timed {args.steps} steps in {elapsed:.2f}s, {psteps} particle pushes, "
+          f"alive {m1['alive']}", file=sys.stderr, flush=True)
+
+    bpp = BYTES_PER_PUSH[args.precision]
+    avg_launch_s = (push_ms / 1e3) / max(launches, 1)
+    bytes_per_launch = bpp * psteps / max(launches, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            t = json.load(open(TRAFFIC_FILE))
+            if t.get("workload") == args.workload and t.get("precision") == args.precision:
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_push", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                "bytes_per_push": bpp}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        swl = wl.scaled(args.cpu_scale)
+        o = O.Oracle(swl, sig, thr, loss, precision=args.precision)
+        _, _, ms0 = o.counters()
+        c0 = time.perf_counter()
+        o.step(args.cpu_steps)
+        ce = time.perf_counter() - c0
+        _, _, ms1 = o.counters()
+        cpu = {"value": round((ms1["psteps"] - ms0["psteps"]) / ce, 1), "unit": "particle-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{args.workload} discharge with every population scaled by {args.cpu_scale:g} "
+                         f"({sum(swl.n_init)} particles), {args.cpu_steps} steps from the initial load, "
+                         f"single-threaded C oracle ({args.precision})"}
+        o.close()
+
+    out = {
+        "metric": "particle-steps/s (gather+push+MCC+deposit)",
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl.gap_m * 100:g} cm, {wl.n_cells} cells, {wl.pressure_Pa:g} Pa, "
+                               f"{wl.voltage_V:g} V, {wl.frequency_Hz / 1e6:g} MHz, dt=T/{wl.steps_per_period}, "
+                               f"{sum(wl.n_init)} macro particles {tuple(wl.n_init)}",
+                   "ion_subcycle": wl.ion_subcycle, "sort_every": wl.sort_every, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    d.close()
+
+
+if __name__ == "__main__":
+    main()

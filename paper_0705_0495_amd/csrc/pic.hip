@@ -5,7 +5,7 @@
 // kernels of each step on one HIP stream:
 //   k_field    field solve + diagnostics              (1 workgroup)
 //   k_push     fused gather/push/absorb/MCC/deposit   (persistent grid)
-//   k_claims   partner reactions                      (small grid, exits at once when idle)
+//   k_tail     partner reactions + bucketing of births (1 workgroup)
 //   k_births   canonical ids, append, close the step  (small grid)
 //   k_sort_*   every sort_every steps
 // Nothing in a step waits for the host.
@@ -112,7 +112,7 @@ struct Impl : Base {
   Consts<R> C;
   Dev<R> D;
   std::vector<void*> allocs;
-  int grid_push = 0, grid_push_default = 0, grid_small = 64, grid_scatter = 0;
+  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0;
   int64_t nstep = 0;  // steps enqueued
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
@@ -257,6 +257,9 @@ struct Impl : Base {
     D.nb_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(65536, totcap / 32), 1 << 24);
     if ((rc = alloc(&D.nb, (size_t)D.nb_cap))) return rc;
     if ((rc = alloc(&D.nbc, 4))) return rc;
+    if ((rc = alloc(&D.bhist, (size_t)NBUCKET))) return rc;
+    if ((rc = alloc(&D.boff, (size_t)NBUCKET + 1))) return rc;
+    if ((rc = alloc(&D.perm, (size_t)D.nb_cap))) return rc;
     D.req_cap = REQ_CAP;
     if ((rc = alloc(&D.req, (size_t)D.req_cap))) return rc;
     if ((rc = alloc(&D.nreq, 1))) return rc;
@@ -292,7 +295,7 @@ struct Impl : Base {
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
-    grid_scatter = std::max(1, ncu * 8);
+    grid_scatter = std::max(1, ncu * 4);
 
     // initial load, deposit, field at t = 0, half step back, first sort
     const int64_t tot = G.n_init[0] + G.n_init[1] + G.n_init[2];
@@ -302,7 +305,7 @@ struct Impl : Base {
       hipLaunchKernelGGL(k_load<R>, dim3(g), dim3(b), 0, c->stream, C, D, G.n_init[0], G.n_init[1], G.n_init[2]);
       hipLaunchKernelGGL(k_deposit_all<R>, dim3(g), dim3(b), 0, c->stream, C, D);
     }
-    hipLaunchKernelGGL(k_field<R>, dim3(1), dim3(FIELD_TPB), 0, c->stream, C, D, 0);
+    HIPCHK(c, launch_field(C, D, 0, c->stream));
     if (tot > 0) {
       const int b = 256;
       const int g = (int)((tot + b - 1) / b);
@@ -329,7 +332,7 @@ struct Impl : Base {
   int step(int64_t nsteps) override {
     const int sort_every = c->G.sort_every;
     for (int64_t k = 0; k < nsteps; k++) {
-      hipLaunchKernelGGL(k_field<R>, dim3(1), dim3(FIELD_TPB), 0, c->stream, C, D, 1);
+      HIPCHK(c, launch_field(C, D, 1, c->stream));
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (c->timing) {
         if (c->ev_used == c->events.size()) {
@@ -345,15 +348,15 @@ struct Impl : Base {
       }
       hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
-      hipLaunchKernelGGL(k_claims<R>, dim3(grid_small), dim3(CLAIM_TPB), 0, c->stream, C, D);
-      hipLaunchKernelGGL(k_births<R>, dim3(grid_small), dim3(BIRTH_TPB), 0, c->stream, C, D);
+      hipLaunchKernelGGL(k_tail<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, C, D);
+      hipLaunchKernelGGL(k_births<R>, dim3(grid_births), dim3(BIRTH_TPB), 0, c->stream, C, D);
       HIPCHK(c, hipGetLastError());
       nstep++;
       if (nstep % sort_every == 0) {
         int rc = sort();
         if (rc) return rc;
       }
-      if (c->timing && c->ev_used >= 4096) {
+      if (c->timing && c->ev_used >= 16384) {
         int rc = drain_events();
         if (rc) return rc;
       }
@@ -471,12 +474,16 @@ struct Impl : Base {
     m->particle_steps = h.psteps;
     m->births = h.births;
     m->next_id = h.next_id;
-    // alive counts: the store lengths include dead slots until the next sort
-    for (int s = 0; s < 3; s++) {
-      int64_t tmp = 0;
-      int rc = particles(s, 0, nullptr, nullptr, nullptr, nullptr, &tmp);
-      if (rc) return rc;
-      m->alive[s] = tmp;
+    // alive counts: between steps the per-cell counts hold exactly the alive particles
+    {
+      std::vector<int32_t> cnt(3 * (size_t)N);
+      HIPCHK(c, hipMemcpyAsync(cnt.data(), D.cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (int s = 0; s < 3; s++) {
+        int64_t tot = 0;
+        for (int i = 0; i < N; i++) tot += cnt[(size_t)s * N + i];
+        m->alive[s] = tot;
+      }
     }
     const double Mst = (double)c->G.steps_per_period;
     const double dx = c->G.gap_m / (double)N;

@@ -25,6 +25,8 @@ constexpr int WIN = 512;               // cells of the LDS deposit window
 constexpr int EEDF_MAX = 256;
 constexpr int FNEG_MAX = 2048;
 constexpr int REQ_CAP = 4096;          // partner requests per step
+constexpr int NBUCKET_BITS = 14;       // births are bucketed by the top bits of the creator id
+constexpr int NBUCKET = 1 << NBUCKET_BITS;
 constexpr uint64_t ID_MASK = (1ull << 40) - 1;
 constexpr uint64_t F_MASK = (1ull << 40) - 1;
 constexpr double TWO_PI = 6.283185307179586;
@@ -103,6 +105,9 @@ struct Dev {
   Birth<R>* nb;
   int32_t nb_cap, req_cap;
   int32_t* nbc;     // [4] total, per species
+  int32_t* bhist;   // [NBUCKET] births per creator-id bucket
+  int32_t* boff;    // [NBUCKET+1]
+  int32_t* perm;    // [nb_cap] births grouped by bucket
   Request<R>* req;
   int32_t* nreq;
   Counters* ctr;
@@ -250,14 +255,19 @@ __device__ __forceinline__ void deposit_global(const Dev<R>& D, int N, int sp, i
   atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)(int64_t)(sign * (int64_t)f));
 }
 
+__device__ __forceinline__ int birth_bucket(uint64_t creator, uint64_t next_id) {
+  const int bits = 64 - __clzll((long long)(next_id | 1));
+  const int sh = bits > NBUCKET_BITS ? bits - NBUCKET_BITS : 0;
+  return (int)(creator >> sh);
+}
+
 template <class R>
 __device__ void add_birth(const Consts<R>& C, const Dev<R>& D, int sp, uint64_t creator, int k, int cell, R off,
                           R v0, R v1, R v2) {
   int b = atomicAdd(&D.nbc[0], 1);
   int bs = atomicAdd(&D.nbc[1 + sp], 1);
-  if (b >= D.nb_cap || D.N[sp] + bs >= D.cap[sp]) {
+  if (b >= D.nb_cap) {
     atomicOr(&D.ctr->err, ERR_NB);
-    if (b < D.nb_cap) D.nb[b].sp = -1;
     return;
   }
   Birth<R> r;
@@ -270,8 +280,14 @@ __device__ void add_birth(const Consts<R>& C, const Dev<R>& D, int sp, uint64_t 
   r.v0 = v0;
   r.v1 = v1;
   r.v2 = v2;
+  if (D.N[sp] + bs >= D.cap[sp]) {
+    atomicOr(&D.ctr->err, ERR_NB);
+    r.sp = -1;
+    r.creator = 0;
+  }
   D.nb[b] = r;
-  deposit_global(D, C.N, sp, cell, off, 1);
+  atomicAdd(&D.bhist[birth_bucket(r.creator, (uint64_t)D.ctr->next_id)], 1);
+  if (r.sp >= 0) deposit_global(D, C.N, sp, cell, off, 1);
 }
 
 template <class R>
@@ -306,9 +322,13 @@ __device__ __forceinline__ void ee_elastic(R va[3], R vb[3], const R n[3]) {
 constexpr int FIELD_TPB = 1024;
 constexpr int NMAX_CELLS = 8192;
 
+constexpr int FIELD_PER_MAX = (NMAX_CELLS + FIELD_TPB) / FIELD_TPB;
+
 // mode 0: solve only (creation); mode 1: step (diagnostics, clear the
-// accumulators of the species moved in this step)
-template <class R>
+// accumulators of the species moved in this step).  A single workgroup; each
+// thread owns PER consecutive nodes and issues all of its loads before any
+// dependent arithmetic, so the kernel waits for one memory round trip.
+template <class R, int PER>
 __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
   __shared__ double phis[NMAX_CELLS + 1];
   __shared__ __int128 scA[FIELD_TPB];
@@ -318,23 +338,43 @@ __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int 
   const int64_t n = D.ctr->step;
   const double U = D.U[n % C.M];
   const bool ion = (n % C.nsub) == 0;
-  const int per = (N + 1 + FIELD_TPB - 1) / FIELD_TPB;
-  const int i0 = tid * per;
-  const int i1 = min(i0 + per, N + 1);
-  int64_t qloc[(NMAX_CELLS + FIELD_TPB) / FIELD_TPB];
+  const int i0 = min(tid * PER, N + 1);
+  const int i1 = min(i0 + PER, N + 1);
+  int32_t cn[3][PER];
+  int64_t Fc[3][PER];
+  int64_t Fp[3];
+  double pa[PER];
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    Fp[s] = (i0 >= 1 && i0 < i1) ? D.F[s * N + i0 - 1] : 0;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = i0 + k;
+      const bool in = i < i1 && i < N;
+      cn[s][k] = in ? D.cnt[s * N + i] : 0;
+      Fc[s][k] = in ? D.F[s * N + i] : 0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; k++) pa[k] = (i0 + k < i1 && mode == 1) ? D.phiacc[i0 + k] : 0.0;
+  int64_t qloc[PER];
   __int128 a = 0, b = 0;
-  for (int i = i0; i < i1; i++) {
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = i0 + k;
+    qloc[k] = 0;
+    if (i >= i1) continue;
     int64_t Qs[3];
 #pragma unroll
     for (int s = 0; s < 3; s++) {
-      int64_t v = 0;
-      if (i < N) v += ((int64_t)D.cnt[s * N + i] << 24) - D.F[s * N + i];
-      if (i >= 1) v += D.F[s * N + i - 1];
+      int64_t v = ((int64_t)cn[s][k] << 24) - Fc[s][k];
+      v += (k == 0) ? Fp[s] : Fc[s][k - 1];
       Qs[s] = v;
-      if (mode == 1) D.Qacc[s * (N + 1) + i] += v;
+      // one addition per node and step: the order of the sums is fixed
+      if (mode == 1) atomicAdd((unsigned long long*)&D.Qacc[s * (N + 1) + i], (unsigned long long)v);
     }
-    int64_t q = (Qs[2] - Qs[0]) - Qs[1];
-    qloc[i - i0] = q;
+    const int64_t q = (Qs[2] - Qs[0]) - Qs[1];
+    qloc[k] = q;
     if (i >= 1 && i <= N - 1) {
       a += (__int128)i * q;
       b += (__int128)(N - i) * q;
@@ -357,8 +397,11 @@ __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int 
   __int128 S1 = scA[tid] - a;   // sum_{j < i0} j q_j
   __int128 PB = scB[tid] - b;   // sum_{j < i0} (N-j) q_j
   const __int128 TB = scB[FIELD_TPB - 1];
-  for (int i = i0; i < i1; i++) {
-    int64_t q = qloc[i - i0];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = i0 + k;
+    if (i >= i1) continue;
+    const int64_t q = qloc[k];
     if (i >= 1 && i <= N - 1) {
       S1 += (__int128)i * q;
       PB += (__int128)(N - i) * q;
@@ -367,37 +410,60 @@ __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int 
     if (i == 0) ph = U;
     else if (i == N) ph = 0.0;
     else {
-      __int128 S2 = TB - PB;  // sum_{j > i} (N-j) q_j
-      __int128 T = (__int128)(N - i) * S1 + (__int128)i * S2;
-      double x = U * (double)(N - i);
-      double y = C.cphi * i128_to_double(T);
+      const __int128 S2 = TB - PB;  // sum_{j > i} (N-j) q_j
+      const __int128 T = (__int128)(N - i) * S1 + (__int128)i * S2;
+      const double x = U * (double)(N - i);
+      const double y = C.cphi * i128_to_double(T);
       ph = (x + y) / (double)N;
     }
     phis[i] = ph;
   }
-  __syncthreads();
-  for (int i = i0; i < i1; i++) {
-    double e;
-    if (i == 0) e = (phis[0] - phis[1]) * C.invdx - C.cE * (double)qloc[0];
-    else if (i == N) e = (phis[N - 1] - phis[N]) * C.invdx + C.cE * (double)qloc[i - i0];
-    else e = (phis[i - 1] - phis[i + 1]) * C.inv2dx;
-    D.E[i] = e;
-    D.phi[i] = phis[i];
-    R er = (R)e;
-    if (i < N) D.E2[2 * i] = er;
-    if (i >= 1) D.E2[2 * (i - 1) + 1] = er;
-    if (mode == 1) D.phiacc[i] += phis[i];
-  }
   if (mode == 1) {
     // the passes of this step deposit every moved particle afresh
+#pragma unroll
     for (int s = 0; s < 3; s++) {
       if (s != 0 && !ion) continue;
-      for (int i = tid; i < N; i += FIELD_TPB) {
-        D.cnt[s * N + i] = 0;
-        D.F[s * N + i] = 0;
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int i = i0 + k;
+        if (i < i1 && i < N) {
+          D.cnt[s * N + i] = 0;
+          D.F[s * N + i] = 0;
+        }
       }
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = i0 + k;
+    if (i >= i1) continue;
+    double e;
+    if (i == 0) e = (phis[0] - phis[1]) * C.invdx - C.cE * (double)qloc[k];
+    else if (i == N) e = (phis[N - 1] - phis[N]) * C.invdx + C.cE * (double)qloc[k];
+    else e = (phis[i - 1] - phis[i + 1]) * C.inv2dx;
+    D.E[i] = e;
+    D.phi[i] = phis[i];
+    const R er = (R)e;
+    if (i < N) D.E2[2 * i] = er;
+    if (i >= 1) D.E2[2 * (i - 1) + 1] = er;
+    if (mode == 1) D.phiacc[i] = pa[k] + phis[i];
+  }
+}
+
+template <class R>
+inline hipError_t launch_field(const Consts<R>& C, const Dev<R>& D, int mode, hipStream_t st) {
+  const int per = (C.N + 1 + FIELD_TPB - 1) / FIELD_TPB;
+  switch (per) {
+    case 1: hipLaunchKernelGGL((k_field<R, 1>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    case 2: hipLaunchKernelGGL((k_field<R, 2>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    case 3: hipLaunchKernelGGL((k_field<R, 3>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    case 4: hipLaunchKernelGGL((k_field<R, 4>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    case 5: hipLaunchKernelGGL((k_field<R, 5>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    case 6: case 7: hipLaunchKernelGGL((k_field<R, 7>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+    default: hipLaunchKernelGGL((k_field<R, FIELD_PER_MAX>), dim3(1), dim3(FIELD_TPB), 0, st, C, D, mode); break;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -822,44 +888,44 @@ __device__ __forceinline__ bool last_block(uint32_t* counter) {
 }
 
 // ---------------------------------------------------------------------------
-// partner reactions (13), (14), (19): partner pick in the cell segment of the
-// last sort, acceptance sigma g / M_j, claims (smallest test id wins; electron
-// requests before O- requests), kinematics, births and charge corrections
+// end of the step, one workgroup:
+//  1. partner reactions (13), (14), (19): pick in the cell segment of the last
+//     sort, acceptance sigma g / M_j, claims (smallest test id wins; electron
+//     requests before O- requests), kinematics, births, charge corrections;
+//  2. births: counting sort of this step's births over creator-id buckets
 // ---------------------------------------------------------------------------
-constexpr int CLAIM_TPB = 256;
+constexpr int TAIL_TPB = 1024;
 
 template <class R>
 __device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int slot) {
   const Store<R> st = D.st[sp];
-  int cell = st.cell[slot];
+  const int cell = st.cell[slot];
   if (cell == DEAD) return;
-  R off = st.off[slot];
+  const R off = st.off[slot];
   deposit_global(D, C.N, sp, cell, off, -1);
   st.cell[slot] = DEAD;
 }
 
+struct ClaimLds {
+  int32_t rpart[REQ_CAP];
+  uint64_t rid[REQ_CAP];
+  uint8_t racc[REQ_CAP];
+  uint8_t rwin[REQ_CAP];
+};
+
 template <class R>
-__global__ void __launch_bounds__(CLAIM_TPB) k_claims(Consts<R> C, Dev<R> D) {
-  __shared__ uint64_t bk[CLAIM_TPB];
-  __shared__ int32_t bi[CLAIM_TPB];
-  __shared__ int32_t rpart[REQ_CAP];
-  __shared__ uint64_t rid[REQ_CAP];
-  __shared__ uint8_t racc[REQ_CAP];
-  __shared__ uint8_t rwin[REQ_CAP];
+__device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, uint64_t* bk, int32_t* bi, int nr,
+                               uint32_t n) {
   const int tid = threadIdx.x;
-  int nr = *D.nreq;
-  if (nr == 0) return;
-  if (nr > D.req_cap) nr = D.req_cap;
   const int N = C.N;
-  const uint32_t n = (uint32_t)D.ctr->step;
-  for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+  for (int r = 0; r < nr; r++) {
     const Request<R> q = D.req[r];
     const int t = (q.chan == 13) ? 1 : 2;
     const int32_t lo = D.seg[t * (N + 1) + q.cell], hi = D.seg[t * (N + 1) + q.cell + 1];
     uint64_t best = ~0ull;
     int32_t bslot = -1;
-    for (int32_t i = lo + tid; i < hi; i += CLAIM_TPB) {
-      uint64_t k = pick_key(C, D.st[t].id[i], q.id, n);
+    for (int32_t i = lo + tid; i < hi; i += TAIL_TPB) {
+      const uint64_t k = pick_key(C, D.st[t].id[i], q.id, n);
       if (k < best) {
         best = k;
         bslot = i;
@@ -868,7 +934,7 @@ __global__ void __launch_bounds__(CLAIM_TPB) k_claims(Consts<R> C, Dev<R> D) {
     bk[tid] = best;
     bi[tid] = bslot;
     __syncthreads();
-    for (int d = CLAIM_TPB / 2; d > 0; d >>= 1) {
+    for (int d = TAIL_TPB / 2; d > 0; d >>= 1) {
       if (tid < d && bk[tid + d] < bk[tid]) {
         bk[tid] = bk[tid + d];
         bi[tid] = bi[tid + d];
@@ -876,80 +942,69 @@ __global__ void __launch_bounds__(CLAIM_TPB) k_claims(Consts<R> C, Dev<R> D) {
       __syncthreads();
     }
     if (tid == 0) {
-      int32_t p = bi[0];
+      const int32_t p = bi[0];
       int acc = 0;
       if (p >= 0 && D.st[t].cell[p] != DEAD) {
         const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
         const Store<R> ts = D.st[q.sp], ps = D.st[t];
-        R gx = ts.vx[q.slot] - ps.vx[p], gy = ts.vy[q.slot] - ps.vy[p], gz = ts.vz[q.slot] - ps.vz[p];
-        R g2 = (gx * gx + gy * gy) + gz * gz;
-        R g = Sqrt(g2);
-        R Erel = C.hmu_c[pi] * g2;
+        const R gx = ts.vx[q.slot] - ps.vx[p], gy = ts.vy[q.slot] - ps.vy[p], gz = ts.vz[q.slot] - ps.vz[p];
+        const R g2 = (gx * gx + gy * gy) + gz * gz;
+        const R g = Sqrt(g2);
+        const R Erel = C.hmu_c[pi] * g2;
         R sg = 0;
         if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, q.chan, lookup(Erel)) * g;
         acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
       }
-      D.req[r].partner = p;
-      D.req[r].acc = acc;
+      L.rpart[r] = p;
+      L.rid[r] = q.id;
+      L.racc[r] = (uint8_t)acc;
+      L.rwin[r] = 0;
     }
     __syncthreads();
   }
-  if (!last_block(&D.done[0])) return;
-  if (tid == 0) D.done[0] = 0;
-  // ---- serial part, one workgroup ----
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    Request<R> q = D.req[r];
-    rpart[r] = q.partner;
-    rid[r] = q.id;
-    racc[r] = (uint8_t)q.acc;
-    rwin[r] = 0;
-  }
-  __syncthreads();
-  // stage 1: electron test particles, partner species differ by channel
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    const Request<R> q = D.req[r];
-    if (q.sp != 0 || !racc[r]) continue;
+  // stage 1: electron test particles; (13) takes an O2+, (19) an O-
+  for (int r = tid; r < nr; r += TAIL_TPB) {
+    const int chan = D.req[r].chan;
+    if (D.req[r].sp != 0 || !L.racc[r]) continue;
     int win = 1;
     for (int r2 = 0; r2 < nr && win; r2++) {
-      if (r2 == r || !racc[r2]) continue;
-      const int c2 = D.req[r2].chan;
-      if (c2 != q.chan) continue;  // (13) takes O2+, (19) takes O-
-      if (rpart[r2] == rpart[r] && rid[r2] < rid[r]) win = 0;
+      if (r2 == r || !L.racc[r2] || D.req[r2].chan != chan) continue;
+      if (L.rpart[r2] == L.rpart[r] && L.rid[r2] < L.rid[r]) win = 0;
     }
-    rwin[r] = (uint8_t)win;
+    L.rwin[r] = (uint8_t)win;
   }
   __syncthreads();
   int nacc = 0;
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    if (!rwin[r]) continue;
+  for (int r = tid; r < nr; r += TAIL_TPB) {
+    if (!L.rwin[r]) continue;
     const Request<R> q = D.req[r];
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[q.chan], 1ull);
     if (q.chan == 12) {
       kill_particle(C, D, 0, q.slot);
-      kill_particle(C, D, 2, q.partner);
+      kill_particle(C, D, 2, L.rpart[r]);
       continue;
     }
     // (19): inelastic e-O- collision, O- split into O + e, e-e elastic
     const Store<R> es = D.st[0], ns = D.st[1];
-    const int p = q.partner;
-    R T[3] = {es.vx[q.slot], es.vy[q.slot], es.vz[q.slot]};
-    R P[3] = {ns.vx[p], ns.vy[p], ns.vz[p]};
+    const int p = L.rpart[r];
+    const R T[3] = {es.vx[q.slot], es.vy[q.slot], es.vz[q.slot]};
+    const R P[3] = {ns.vx[p], ns.vy[p], ns.vz[p]};
     const R a = C.a_c[1], b = C.b_c[1];
-    R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
-    R g2 = (gx * gx + gy * gy) + gz * gz;
-    R Erel = C.hmu_c[1] * g2;
-    uint4 w = rng(C, q.id, n, 2);
+    const R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
+    const R g2 = (gx * gx + gy * gy) + gz * gz;
+    const R Erel = C.hmu_c[1] * g2;
+    const uint4 w = rng(C, q.id, n, 2);
     R n1[3], n2[3];
     iso_dir<R>(w.x, w.y, n1);
     iso_dir<R>(w.z, w.w, n2);
-    R Ep = Erel - C.loss[13];
-    R gp = Sqrt(Ep * C.c2e_c[1]);
-    R ag = a * gp, bg = b * gp;
+    const R Ep = Erel - C.loss[13];
+    const R gp = Sqrt(Ep * C.c2e_c[1]);
+    const R ag = a * gp, bg = b * gp;
     R ve[3], vn[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      R vc = b * T[d] + a * P[d];
+      const R vc = b * T[d] + a * P[d];
       ve[d] = vc + ag * n1[d];
       vn[d] = vc - bg * n1[d];
     }
@@ -965,71 +1020,118 @@ __global__ void __launch_bounds__(CLAIM_TPB) k_claims(Consts<R> C, Dev<R> D) {
   __syncthreads();
   // stage 2: O- test particles (14); the O- must not have been taken by a
   // (19) winner and the O2+ not by a (13) winner
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    const Request<R> q = D.req[r];
-    if (q.sp != 1 || !racc[r]) continue;
+  for (int r = tid; r < nr; r += TAIL_TPB) {
+    if (D.req[r].sp != 1 || !L.racc[r]) continue;
+    const int slot = D.req[r].slot;
     int ok = 1;
     for (int r2 = 0; r2 < nr && ok; r2++) {
-      if (!rwin[r2]) continue;
+      if (L.rwin[r2] != 1) continue;
       const int c2 = D.req[r2].chan;
-      if (c2 == 13 && rpart[r2] == q.slot) ok = 0;
-      if (c2 == 12 && rpart[r2] == rpart[r]) ok = 0;
+      if (c2 == 13 && L.rpart[r2] == slot) ok = 0;
+      if (c2 == 12 && L.rpart[r2] == L.rpart[r]) ok = 0;
     }
-    racc[r] = (uint8_t)(ok ? 2 : 0);
+    L.racc[r] = (uint8_t)(ok ? 2 : 0);
   }
   __syncthreads();
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    if (racc[r] != 2) continue;
+  for (int r = tid; r < nr; r += TAIL_TPB) {
+    if (L.racc[r] != 2) continue;
     int win = 1;
     for (int r2 = 0; r2 < nr && win; r2++) {
-      if (r2 == r || racc[r2] != 2) continue;
-      if (rpart[r2] == rpart[r] && rid[r2] < rid[r]) win = 0;
+      if (r2 == r || L.racc[r2] != 2) continue;
+      if (L.rpart[r2] == L.rpart[r] && L.rid[r2] < L.rid[r]) win = 0;
     }
-    rwin[r] = (uint8_t)(win ? 3 : 0);
+    if (win) L.rwin[r] = 3;
   }
   __syncthreads();
-  for (int r = tid; r < nr; r += CLAIM_TPB) {
-    if (rwin[r] != 3) continue;
+  for (int r = tid; r < nr; r += TAIL_TPB) {
+    if (L.rwin[r] != 3) continue;
     const Request<R> q = D.req[r];
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[17], 1ull);
     kill_particle(C, D, 1, q.slot);
-    kill_particle(C, D, 2, q.partner);
+    kill_particle(C, D, 2, L.rpart[r]);
   }
   if (nacc) atomicAdd((unsigned long long*)&D.ctr->nacc, (unsigned long long)nacc);
   if (tid == 0) atomicAdd((unsigned long long*)&D.ctr->nreq, (unsigned long long)nr);
 }
 
+template <class R>
+__global__ void __launch_bounds__(TAIL_TPB) k_tail(Consts<R> C, Dev<R> D) {
+  __shared__ union {
+    ClaimLds claims;
+    int32_t cur[NBUCKET];
+  } U;
+  __shared__ uint64_t bk[TAIL_TPB];
+  __shared__ int32_t bi[TAIL_TPB];
+  const int tid = threadIdx.x;
+  int nr = *D.nreq;
+  if (nr > D.req_cap) nr = D.req_cap;
+  if (nr > 0) {
+    resolve_claims(C, D, U.claims, bk, bi, nr, (uint32_t)D.ctr->step);
+    __threadfence();
+    __syncthreads();
+  }
+  int B = D.nbc[0];
+  if (B > D.nb_cap) B = D.nb_cap;
+  if (B == 0) return;
+  constexpr int PER = NBUCKET / TAIL_TPB;
+  int loc[PER];
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    loc[q] = D.bhist[tid * PER + q];
+    sum += loc[q];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; q++) D.bhist[tid * PER + q] = 0;
+  bi[tid] = sum;
+  __syncthreads();
+  for (int d = 1; d < TAIL_TPB; d <<= 1) {
+    const int x = tid >= d ? bi[tid - d] : 0;
+    __syncthreads();
+    bi[tid] += x;
+    __syncthreads();
+  }
+  int run = bi[tid] - sum;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    D.boff[tid * PER + q] = run;
+    U.cur[tid * PER + q] = run;
+    run += loc[q];
+  }
+  if (tid == TAIL_TPB - 1) D.boff[NBUCKET] = run;
+  __syncthreads();
+  const uint64_t nid = (uint64_t)D.ctr->next_id;
+  for (int b = tid; b < B; b += TAIL_TPB) {
+    const int bkt = birth_bucket(D.nb[b].creator, nid);
+    const int slot = atomicAdd(&U.cur[bkt], 1);
+    D.perm[slot] = b;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// births: canonical ids (rank by creator id, then k), append to the stores;
-// the last workgroup closes the step
+// births: canonical ids (rank by creator id, then k) inside the creator-id
+// bucket; append to the stores; the last workgroup closes the step
 // ---------------------------------------------------------------------------
 constexpr int BIRTH_TPB = 256;
 
 template <class R>
 __global__ void __launch_bounds__(BIRTH_TPB) k_births(Consts<R> C, Dev<R> D) {
-  __shared__ uint64_t keys[BIRTH_TPB];
   const int tid = threadIdx.x;
   int B = D.nbc[0];
   if (B > D.nb_cap) B = D.nb_cap;
   const uint64_t next = (uint64_t)D.ctr->next_id;
-  for (int b0 = blockIdx.x * BIRTH_TPB; b0 < B; b0 += gridDim.x * BIRTH_TPB) {
-    const int b = b0 + tid;
-    uint64_t key = ~0ull;
-    Birth<R> rec;
-    if (b < B) {
-      rec = D.nb[b];
-      key = (rec.creator << 1) | (uint64_t)rec.k;
+  for (int b = blockIdx.x * BIRTH_TPB + tid; b < B; b += gridDim.x * BIRTH_TPB) {
+    const Birth<R> rec = D.nb[b];
+    const uint64_t key = (rec.creator << 2) | (uint64_t)rec.k;
+    const int bk = birth_bucket(rec.creator, next);
+    const int lo = D.boff[bk], hi = D.boff[bk + 1];
+    int rank = lo;
+    for (int i = lo; i < hi; i++) {
+      const Birth<R>& o = D.nb[D.perm[i]];
+      rank += (((o.creator << 2) | (uint64_t)o.k) < key);
     }
-    int rank = 0;
-    for (int t0 = 0; t0 < B; t0 += BIRTH_TPB) {
-      keys[tid] = (t0 + tid < B) ? ((D.nb[t0 + tid].creator << 1) | (uint64_t)D.nb[t0 + tid].k) : ~0ull;
-      __syncthreads();
-      const int m = min(BIRTH_TPB, B - t0);
-      for (int i = 0; i < m; i++) rank += (keys[i] < key);
-      __syncthreads();
-    }
-    if (b < B && rec.sp >= 0) {
+    if (rec.sp >= 0) {
       const int sp = rec.sp;
       const int64_t slot = D.N[sp] + rec.idx;
       if (slot < D.cap[sp]) {
@@ -1134,67 +1236,81 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
   }
 }
 
+constexpr int SORT_TPB = 256;
+constexpr int SORT_PER = 16;
+constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
+constexpr int SORT_WIN = 1024;
+
+// Each workgroup moves one contiguous chunk of a store: ranks inside the chunk
+// come from LDS counters over a window of cells, and one global atomic per
+// (chunk, cell) reserves the destination range.
 template <class R>
-__global__ void __launch_bounds__(256) k_sort_scatter(Consts<R> C, Dev<R> D) {
+__global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D) {
+  __shared__ int32_t lcnt[SORT_WIN];
+  __shared__ int32_t lbase[SORT_WIN];
+  __shared__ int32_t wbase;
   const int N = C.N;
-  const int lane = threadIdx.x & 63;
-  int64_t Ns[3], tot = 0;
+  const int tid = threadIdx.x;
+  int64_t Ns[3], nch[3];
   for (int s = 0; s < 3; s++) {
     Ns[s] = D.N[s];
-    tot += Ns[s];
+    nch[s] = (Ns[s] + SORT_CHUNK - 1) / SORT_CHUNK;
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // wave-uniform loop bound so that every lane takes part in the ballots
-  const int64_t span = ((tot + stride - 1) / stride) * stride;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < span; g += stride) {
+  const int64_t total = nch[0] + nch[1] + nch[2];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
     int s = 0;
-    int64_t i = g;
-    bool valid = g < tot;
-    if (valid) {
-      if (i >= Ns[0]) {
-        i -= Ns[0];
-        s = 1;
-        if (i >= Ns[1]) {
-          i -= Ns[1];
-          s = 2;
-        }
+    int64_t c = t;
+    if (c >= nch[0]) {
+      c -= nch[0];
+      s = 1;
+      if (c >= nch[1]) {
+        c -= nch[1];
+        s = 2;
       }
     }
-    int32_t cell = valid ? D.st[s].cell[i] : DEAD;
-    bool alive = valid && cell != DEAD;
-    // group the lanes of the wave by (species, cell); one atomic per group
-    const int key = alive ? (s * (N + 1) + cell) : -1;
-    uint64_t pending = __ballot(alive);
-    int32_t dst = -1;
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int lkey = __shfl(key, leader);
-      const uint64_t peers = __ballot(key == lkey);
-      const int cnt = __popcll(peers);
-      const int rank = __popcll(peers & ((1ull << lane) - 1));
-      int basei = 0;
-      if (lane == leader) {
-        const int ls = lkey / (N + 1), lc = lkey % (N + 1);
-        basei = atomicAdd(&D.cursor[ls * N + lc], cnt);
-      }
-      basei = __shfl(basei, leader);
-      if (key == lkey) dst = basei + rank;
-      pending &= ~peers;
+    const int64_t c0 = c * SORT_CHUNK;
+    const Store<R> a = D.st[s], b = D.alt[s];
+    int32_t* cur = D.cursor + (size_t)s * N;
+    const int32_t* seg = D.seg + (size_t)s * (N + 1);
+    if (tid == 0) {
+      const int32_t cf = a.cell[c0];
+      wbase = (cf == DEAD ? 0 : cf) - 64;
     }
-    if (alive) {
-      const int32_t lim = D.seg[s * (N + 1) + cell + 1];
-      if (dst < 0 || dst >= lim) {
+    for (int i = tid; i < SORT_WIN; i += SORT_TPB) lcnt[i] = 0;
+    __syncthreads();
+    const int base = wbase;
+    int32_t cell[SORT_PER], rank[SORT_PER];
+#pragma unroll
+    for (int j = 0; j < SORT_PER; j++) {
+      const int64_t slot = c0 + (int64_t)j * SORT_TPB + tid;
+      cell[j] = slot < Ns[s] ? a.cell[slot] : DEAD;
+      rank[j] = -1;
+      if (cell[j] != DEAD) {
+        const int idx = cell[j] - base;
+        if ((unsigned)idx < (unsigned)SORT_WIN) rank[j] = atomicAdd(&lcnt[idx], 1);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < SORT_WIN; i += SORT_TPB)
+      if (lcnt[i] > 0) lbase[i] = atomicAdd(&cur[base + i], lcnt[i]);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_PER; j++) {
+      if (cell[j] == DEAD) continue;
+      const int64_t slot = c0 + (int64_t)j * SORT_TPB + tid;
+      const int32_t dst = rank[j] >= 0 ? lbase[cell[j] - base] + rank[j] : atomicAdd(&cur[cell[j]], 1);
+      if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1]) {
         atomicOr(&D.ctr->err, ERR_SORT);
-      } else {
-        const Store<R> a = D.st[s], b = D.alt[s];
-        b.cell[dst] = cell;
-        b.off[dst] = a.off[i];
-        b.vx[dst] = a.vx[i];
-        b.vy[dst] = a.vy[i];
-        b.vz[dst] = a.vz[i];
-        b.id[dst] = a.id[i];
+        continue;
       }
+      b.cell[dst] = cell[j];
+      b.off[dst] = a.off[slot];
+      b.vx[dst] = a.vx[slot];
+      b.vy[dst] = a.vy[slot];
+      b.vz[dst] = a.vz[slot];
+      b.id[dst] = a.id[slot];
     }
+    __syncthreads();
   }
   if (!last_block(&D.done[2])) return;
   if (threadIdx.x == 0) {
