@@ -4,7 +4,8 @@
 // once to the particle precision), owns the device memory and enqueues the
 // kernels of each step on one HIP stream:
 //   k_field    field solve + diagnostics              (1 workgroup)
-//   k_push     fused gather/push/absorb/MCC/deposit   (persistent grid)
+//   k_push     fused gather/push/absorb/null test/deposit (persistent grid)
+//   k_collide  collisions of the null-test candidates (persistent grid)
 //   k_tail     partner reactions + bucketing of births (1 workgroup)
 //   k_births   canonical ids, append, close the step  (small grid)
 //   k_sort_*   every sort_every steps
@@ -112,7 +113,7 @@ struct Impl : Base {
   Consts<R> C;
   Dev<R> D;
   std::vector<void*> allocs;
-  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0;
+  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0;
   int64_t nstep = 0;  // steps enqueued
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
@@ -260,6 +261,11 @@ struct Impl : Base {
     if ((rc = alloc(&D.bhist, (size_t)NBUCKET))) return rc;
     if ((rc = alloc(&D.boff, (size_t)NBUCKET + 1))) return rc;
     if ((rc = alloc(&D.perm, (size_t)D.nb_cap))) return rc;
+    for (int s = 0; s < 3; s++) {
+      if ((rc = alloc(&D.cand[s], (size_t)D.cap[s] + TILE))) return rc;
+      if ((rc = alloc(&D.tcnt[s], (size_t)(D.cap[s] / TILE + 2)))) return rc;
+    }
+    if ((rc = alloc(&D.ncand, 3))) return rc;
     D.req_cap = REQ_CAP;
     if ((rc = alloc(&D.req, (size_t)D.req_cap))) return rc;
     if ((rc = alloc(&D.nreq, 1))) return rc;
@@ -296,6 +302,7 @@ struct Impl : Base {
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
     grid_scatter = std::max(1, ncu * 4);
+    grid_collide = std::max(1, ncu * 8);
 
     // initial load, deposit, field at t = 0, half step back, first sort
     const int64_t tot = G.n_init[0] + G.n_init[1] + G.n_init[2];
@@ -348,6 +355,7 @@ struct Impl : Base {
       }
       hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+      hipLaunchKernelGGL(k_collide<R>, dim3(grid_collide), dim3(COLL_TPB), 0, c->stream, C, D);
       hipLaunchKernelGGL(k_tail<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, C, D);
       hipLaunchKernelGGL(k_births<R>, dim3(grid_births), dim3(BIRTH_TPB), 0, c->stream, C, D);
       HIPCHK(c, hipGetLastError());

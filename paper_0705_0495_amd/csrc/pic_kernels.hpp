@@ -108,6 +108,10 @@ struct Dev {
   int32_t* bhist;   // [NBUCKET] births per creator-id bucket
   int32_t* boff;    // [NBUCKET+1]
   int32_t* perm;    // [nb_cap] births grouped by bucket
+  int32_t* cand[3]; // candidates of the null-collision test: tile t of species s
+                    // writes its slots to cand[s][t*TILE ...]
+  int32_t* tcnt[3]; // candidates per tile
+  int32_t* ncand;   // [3] (unused)
   Request<R>* req;
   int32_t* nreq;
   Counters* ctr;
@@ -467,68 +471,76 @@ inline hipError_t launch_field(const Consts<R>& C, const Dev<R>& D, int mode, hi
 }
 
 // ---------------------------------------------------------------------------
-// fused push + null-collision MCC + deposit
+// diagnostics accumulated per workgroup in LDS
 // ---------------------------------------------------------------------------
-template <class R>
-struct QEntry {
-  int32_t slot, cell;
-  R off, vx;
-};
-
-template <class R>
-struct PushLds {
-  uint64_t win[WIN];
-  QEntry<R> q[TILE];
+struct DiagLds {
   int32_t eedf[EEDF_MAX + 1];
   int32_t fneg[FNEG_MAX];
   int32_t ev[NCH];
   int32_t absorbed[6];
   int32_t tophits;
-  int32_t qn;
-  int32_t base;
   int32_t psteps;
 };
 
+__device__ inline void diag_init(DiagLds& G) {
+  for (int i = threadIdx.x; i < EEDF_MAX + 1; i += blockDim.x) G.eedf[i] = 0;
+  for (int i = threadIdx.x; i < FNEG_MAX; i += blockDim.x) G.fneg[i] = 0;
+  if (threadIdx.x < NCH) G.ev[threadIdx.x] = 0;
+  if (threadIdx.x < 6) G.absorbed[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    G.tophits = 0;
+    G.psteps = 0;
+  }
+}
+
+template <class R>
+__device__ inline void diag_flush(const Consts<R>& C, const Dev<R>& D, DiagLds& G) {
+  const int tid = threadIdx.x;
+  if (tid == 0 && G.psteps) atomicAdd((unsigned long long*)&D.ctr->psteps, (unsigned long long)G.psteps);
+  if (tid < NCH && G.ev[tid]) atomicAdd((unsigned long long*)&D.ctr->events[tid], (unsigned long long)G.ev[tid]);
+  if (tid < 6 && G.absorbed[tid])
+    atomicAdd((unsigned long long*)&D.ctr->absorbed[tid], (unsigned long long)G.absorbed[tid]);
+  if (tid == 0 && G.tophits) atomicAdd((unsigned long long*)&D.ctr->tophits, (unsigned long long)G.tophits);
+  if (C.eedf_bins > 0)
+    for (int i = tid; i <= C.eedf_bins; i += blockDim.x)
+      if (G.eedf[i]) atomicAdd((unsigned long long*)&D.eedf_acc[i], (unsigned long long)G.eedf[i]);
+  const int nf = C.fneg_xbins * C.fneg_ebins;
+  for (int i = tid; i < nf; i += blockDim.x)
+    if (G.fneg[i]) atomicAdd((unsigned long long*)&D.fneg_acc[i], (unsigned long long)G.fneg[i]);
+}
+
 template <class R, int S>
-__device__ __forceinline__ void diag_alive(const Consts<R>& C, PushLds<R>& L, int cell, R vx, R vy, R vz) {
+__device__ __forceinline__ void diag_alive(const Consts<R>& C, DiagLds& G, int cell, R vx, R vy, R vz) {
   if (S == 0) {
     if (cell == C.cmid && C.eedf_bins > 0) {
-      R e2 = (vx * vx + vy * vy) + vz * vz;
-      R Ek = C.hme * e2;
-      R bf = Ek * C.eedf_sc;
-      int bin = (bf >= (R)C.eedf_bins) ? C.eedf_bins : (int)bf;
-      atomicAdd(&L.eedf[bin], 1);
+      const R e2 = (vx * vx + vy * vy) + vz * vz;
+      const R Ek = C.hme * e2;
+      const R bf = Ek * C.eedf_sc;
+      const int bin = (bf >= (R)C.eedf_bins) ? C.eedf_bins : (int)bf;
+      atomicAdd(&G.eedf[bin], 1);
     }
   } else if (S == 1) {
     if (C.fneg_xbins > 0 && C.fneg_ebins > 0) {
       R Ex = C.hmn * (vx * vx);
       if (vx < (R)0) Ex = -Ex;
-      R bf = (Ex + C.fneg_em) * C.fneg_sc;
-      int eb = bf < (R)0 ? 0 : (bf >= (R)C.fneg_ebins ? C.fneg_ebins - 1 : (int)bf);
-      int xb = (int)(((int64_t)cell * C.fneg_xbins) / C.N);
-      atomicAdd(&L.fneg[xb * C.fneg_ebins + eb], 1);
+      const R bf = (Ex + C.fneg_em) * C.fneg_sc;
+      const int eb = bf < (R)0 ? 0 : (bf >= (R)C.fneg_ebins ? C.fneg_ebins - 1 : (int)bf);
+      const int xb = (int)(((int64_t)cell * C.fneg_xbins) / C.N);
+      atomicAdd(&G.fneg[xb * C.fneg_ebins + eb], 1);
     }
   }
 }
 
-template <class R>
-__device__ __forceinline__ void deposit_win(PushLds<R>& L, const Dev<R>& D, int N, int sp, int base, int cell,
-                                            R off) {
-  int32_t f = frac24(off);
-  int idx = cell - base;
-  if ((unsigned)idx < (unsigned)WIN) {
-    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)((1ull << 40) + (uint64_t)f));
-  } else {
-    atomicAdd(&D.cnt[(size_t)sp * N + cell], 1);
-    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)f);
-  }
-}
-
-// collision with a gas molecule; returns false when the test particle is removed
+// ---------------------------------------------------------------------------
+// collisions of the candidates of the null-collision test (Eq. (1)): channel
+// decision, gas-target and partner reactions, kinematics, births.  The push
+// kernel already deposited every candidate at its post-push position; a
+// candidate that is removed here takes its deposit back.
+// ---------------------------------------------------------------------------
 template <class R, int S>
-__device__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int slot, int cell, R off, uint64_t id,
-                          R v[3], const R vt[3], R g, R Erel, uint32_t n) {
-  uint4 w = rng(C, id, n, 2);
+__device__ __forceinline__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int cell, R off, uint64_t id, R v[3],
+                          const R vt[3], R g, R Erel, uint32_t n) {
+  const uint4 w = rng(C, id, n, 2);
   R n1[3], n2[3];
   iso_dir<R>(w.x, w.y, n1);
   iso_dir<R>(w.z, w.w, n2);
@@ -541,14 +553,14 @@ __device__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int slot, 
     return false;
   }
   if (S == 1 && (j == 15 || j == 16)) {  // (16) direct / (17) associative detachment
-    R f = (j == 15) ? C.ddf : C.adf;
-    R sp = f * g;
+    const R f = (j == 15) ? C.ddf : C.adf;
+    const R sp = f * g;
     add_birth(C, D, 0, id, 0, cell, off, vc[0] + sp * n1[0], vc[1] + sp * n1[1], vc[2] + sp * n1[2]);
     return false;
   }
   R gp = g;
   if (C.loss[j] > (R)0) {
-    R Ep = Erel - C.loss[j];
+    const R Ep = Erel - C.loss[j];
     gp = Sqrt(Ep * C.c2e_g[S]);
   }
   const R ag = a * gp, bg = b * gp;
@@ -574,28 +586,27 @@ __device__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int slot, 
 }
 
 template <class R, int S>
-__device__ void candidate(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, const QEntry<R>& e, uint32_t n,
-                          int base) {
+__device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int slot, uint32_t n) {
   const Store<R> st = D.st[S];
   const int N = C.N;
-  const int slot = e.slot, cell = e.cell;
-  const R off = e.off;
-  R v[3] = {e.vx, st.vy[slot], st.vz[slot]};
+  const int cell = st.cell[slot];
+  const R off = st.off[slot];
+  R v[3] = {st.vx[slot], st.vy[slot], st.vz[slot]};
   const uint64_t id = st.id[slot];
-  uint4 w = rng(C, id, n, 0);
+  const uint4 w = rng(C, id, n, 0);
   const double U = unif52(w.x, w.y);
   double cum = 0.0;
-  // partner channels first: slot size tau n_t(c) M_j (thinned later)
+  // partner channels first: slot size tau n_t(c) M_j (thinned in k_tail)
   constexpr int NP = (S == 0) ? 2 : (S == 1 ? 1 : 0);
 #pragma unroll
   for (int q = 0; q < NP; q++) {
-    const int pi = (S == 0) ? q : 2;             // index into the partner-channel constants
+    const int pi = (S == 0) ? q : 2;
     const int chan = (S == 0) ? 12 + q : 17;
     const int t = (chan == 13) ? 1 : 2;
     const int32_t Lc = D.seg[t * (N + 1) + cell + 1] - D.seg[t * (N + 1) + cell];
     cum = cum + (double)Lc * C.KP[pi];
     if (U < cum) {
-      int r = atomicAdd(D.nreq, 1);
+      const int r = atomicAdd(D.nreq, 1);
       if (r < D.req_cap) {
         Request<R> rq;
         rq.sp = S;
@@ -610,24 +621,23 @@ __device__ void candidate(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, co
       } else {
         atomicOr(&D.ctr->err, ERR_REQ);
       }
-      deposit_win(L, D, N, S, base, cell, off);
-      diag_alive<R, S>(C, L, cell, v[0], v[1], v[2]);
+      diag_alive<R, S>(C, G, cell, v[0], v[1], v[2]);
       return;
     }
   }
   // gas target drawn from the Maxwellian at T_gas
-  uint4 u = rng(C, id, n, 1);
-  R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
-  R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
+  const uint4 u = rng(C, id, n, 1);
+  const R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
+  const R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
   R vt[3];
   vt[0] = C.vthg * (r1 * cos2pi<R>(a1));
   vt[1] = C.vthg * (r1 * sin2pi<R>(a1));
   vt[2] = C.vthg * (r2 * cos2pi<R>(a2));
-  R gx = v[0] - vt[0], gy = v[1] - vt[1], gz = v[2] - vt[2];
-  R g2 = (gx * gx + gy * gy) + gz * gz;
-  R g = Sqrt(g2);
-  R Erel = C.hmu_g[S] * g2;
-  if (Erel >= (R)16384) atomicAdd(&L.tophits, 1);
+  const R gx = v[0] - vt[0], gy = v[1] - vt[1], gz = v[2] - vt[2];
+  const R g2 = (gx * gx + gy * gy) + gz * gz;
+  const R g = Sqrt(g2);
+  const R Erel = C.hmu_g[S] * g2;
+  if (Erel >= (R)16384) atomicAdd(&G.tophits, 1);
   const Lookup<R> Lk = lookup(Erel);
   constexpr int G0 = (S == 0) ? 0 : (S == 1 ? 14 : 18);
   constexpr int NG = (S == 0) ? 12 : (S == 1 ? 3 : 1);
@@ -640,28 +650,86 @@ __device__ void candidate(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, co
     cum = cum + C.PG[j] * (double)sg;
     if (hit < 0 && U < cum) hit = j;
   }
-  bool alive = true;
   if (hit >= 0) {
-    atomicAdd(&L.ev[hit], 1);
-    alive = gas_event<R, S>(C, D, hit, slot, cell, off, id, v, vt, g, Erel, n);
-    if (alive) {
+    atomicAdd(&G.ev[hit], 1);
+    if (gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n)) {
       st.vx[slot] = v[0];
       st.vy[slot] = v[1];
       st.vz[slot] = v[2];
     } else {
       st.cell[slot] = DEAD;
+      deposit_global(D, N, S, cell, off, -1);
+      return;
     }
   }
-  if (alive) {
-    deposit_win(L, D, N, S, base, cell, off);
-    diag_alive<R, S>(C, L, cell, v[0], v[1], v[2]);
-  }
+  diag_alive<R, S>(C, G, cell, v[0], v[1], v[2]);
 }
+
+constexpr int COLL_TPB = 256;
+constexpr int COLL_GROUP = 8;  // tiles per workgroup iteration
+
+template <class R, int S>
+__device__ __forceinline__ void collide_group(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int32_t* pre,
+                                              int64_t tile0, int64_t ntiles, uint32_t n) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int run = 0;
+    for (int k = 0; k < COLL_GROUP; k++) {
+      pre[k] = run;
+      run += (tile0 + k < ntiles) ? D.tcnt[S][tile0 + k] : 0;
+    }
+    pre[COLL_GROUP] = run;
+  }
+  __syncthreads();
+  const int tot = pre[COLL_GROUP];
+  for (int e = tid; e < tot; e += COLL_TPB) {
+    int k = 0;
+    while (e >= pre[k + 1]) k++;
+    const int slot = D.cand[S][(tile0 + k) * TILE + (e - pre[k])];
+    collide_one<R, S>(C, D, G, slot, n);
+  }
+  __syncthreads();
+}
+
+template <class R>
+__global__ void __launch_bounds__(COLL_TPB) k_collide(Consts<R> C, Dev<R> D) {
+  __shared__ DiagLds G;
+  __shared__ int32_t pre[COLL_GROUP + 1];
+  diag_init(G);
+  __syncthreads();
+  const int64_t nstep = D.ctr->step;
+  const uint32_t n = (uint32_t)nstep;
+  const bool ion = (nstep % C.nsub) == 0;
+  int64_t nt[3], ng[3];
+  for (int s = 0; s < 3; s++) {
+    const int64_t Ns = (s == 0 || ion) ? D.N[s] : 0;
+    nt[s] = (Ns + TILE - 1) / TILE;
+    ng[s] = (nt[s] + COLL_GROUP - 1) / COLL_GROUP;
+  }
+  const int64_t total = ng[0] + ng[1] + ng[2];
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    if (g < ng[0]) collide_group<R, 0>(C, D, G, pre, g * COLL_GROUP, nt[0], n);
+    else if (g < ng[0] + ng[1]) collide_group<R, 1>(C, D, G, pre, (g - ng[0]) * COLL_GROUP, nt[1], n);
+    else collide_group<R, 2>(C, D, G, pre, (g - ng[0] - ng[1]) * COLL_GROUP, nt[2], n);
+  }
+  diag_flush(C, D, G);
+}
+
+// ---------------------------------------------------------------------------
+// fused push: gather, leapfrog, absorption, null-collision test, deposit
+// ---------------------------------------------------------------------------
+template <class R>
+struct PushLds {
+  uint64_t win[WIN];
+  DiagLds G;
+  int32_t base;
+  int32_t ncand;
+};
 
 template <class R> struct Vec4;
 template <> struct Vec4<float> {
   static __device__ __forceinline__ void load(const float* p, float o[4]) {
-    float4 v = *(const float4*)p;
+    const float4 v = *(const float4*)p;
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
   static __device__ __forceinline__ void store(float* p, const float o[4]) {
@@ -670,7 +738,7 @@ template <> struct Vec4<float> {
 };
 template <> struct Vec4<double> {
   static __device__ __forceinline__ void load(const double* p, double o[4]) {
-    double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+    const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
   }
   static __device__ __forceinline__ void store(double* p, const double o[4]) {
@@ -679,16 +747,35 @@ template <> struct Vec4<double> {
   }
 };
 
+template <class R>
+__device__ __forceinline__ void deposit_win(PushLds<R>& L, const Dev<R>& D, int N, int sp, int base, int cell,
+                                            R off) {
+  const int32_t f = frac24(off);
+  const int idx = cell - base;
+  if ((unsigned)idx < (unsigned)WIN) {
+    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)((1ull << 40) + (uint64_t)f));
+  } else {
+    atomicAdd(&D.cnt[(size_t)sp * N + cell], 1);
+    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)f);
+  }
+}
+
+struct TileCount {
+  int pushed, abs0, abs1;
+};
+
 template <class R, int S>
-__device__ void push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int64_t t0, int64_t Ns, uint32_t n,
-                          uint64_t T0, double pmax, int* my_abs, int* my_ps) {
+__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int64_t t0,
+                                               int64_t Ns, uint32_t n, uint64_t T0, double pmax) {
+  TileCount tc = {0, 0, 0};
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int N = C.N;
   const Store<R> st = D.st[S];
   if (tid == 0) {
-    int32_t c0 = st.cell[t0];
+    const int32_t c0 = st.cell[t0];
     L.base = (c0 == DEAD ? 0 : c0) - 64;
-    L.qn = 0;
+    L.ncand = 0;
   }
   for (int i = tid; i < WIN; i += TPB) L.win[i] = 0;
   __syncthreads();
@@ -699,33 +786,28 @@ __device__ void push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, in
   uint64_t id[4];
   const bool full = s0 + 3 < Ns;
   if (full) {
-    int4 cv = *(const int4*)(st.cell + s0);
+    const int4 cv = *(const int4*)(st.cell + s0);
     c[0] = cv.x; c[1] = cv.y; c[2] = cv.z; c[3] = cv.w;
     Vec4<R>::load(st.off + s0, off);
     Vec4<R>::load(st.vx + s0, vx);
-    ulonglong2 ia = *(const ulonglong2*)(st.id + s0), ib = *(const ulonglong2*)(st.id + s0 + 2);
+    const ulonglong2 ia = *(const ulonglong2*)(st.id + s0), ib = *(const ulonglong2*)(st.id + s0 + 2);
     id[0] = ia.x; id[1] = ia.y; id[2] = ib.x; id[3] = ib.y;
   } else {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      if (s0 + q < Ns) {
-        c[q] = st.cell[s0 + q];
-        off[q] = st.off[s0 + q];
-        vx[q] = st.vx[s0 + q];
-        id[q] = st.id[s0 + q];
-      } else {
-        c[q] = DEAD;
-        off[q] = 0;
-        vx[q] = 0;
-        id[q] = 0;
-      }
+      const bool in = s0 + q < Ns;
+      c[q] = in ? st.cell[s0 + q] : DEAD;
+      off[q] = in ? st.off[s0 + q] : (R)0;
+      vx[q] = in ? st.vx[s0 + q] : (R)0;
+      id[q] = in ? st.id[s0 + q] : 0;
     }
   }
   const bool was_dead[4] = {c[0] == DEAD, c[1] == DEAD, c[2] == DEAD, c[3] == DEAD};
+  int candmask = 0;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     if (was_dead[q]) continue;
-    (*my_ps)++;
+    tc.pushed++;
     const R E0 = D.E2[2 * c[q]], E1 = D.E2[2 * c[q] + 1];
     const R dE = E1 - E0;
     const R tt = off[q] * dE;
@@ -749,31 +831,23 @@ __device__ void push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, in
     off[q] = o;
     if (cn < 0) {
       c[q] = DEAD;
-      my_abs[0]++;
+      tc.abs0++;
       continue;
     }
     if (cn >= N) {
       c[q] = DEAD;
-      my_abs[1]++;
+      tc.abs1++;
       continue;
     }
     c[q] = cn;
+    deposit_win(L, D, N, S, base, cn, o);
     const uint4 w = rng(C, id[q], n, 0);
     if ((uint64_t)w.x < T0 && unif52(w.x, w.y) < pmax) {
-      int qi = atomicAdd(&L.qn, 1);
-      QEntry<R> e;
-      e.slot = (int32_t)(s0 + q);
-      e.cell = cn;
-      e.off = o;
-      e.vx = vx[q];
-      L.q[qi] = e;
-    } else {
-      deposit_win(L, D, N, S, base, cn, o);
-      if (S == 0) {
-        if (cn == C.cmid) diag_alive<R, S>(C, L, cn, vx[q], st.vy[s0 + q], st.vz[s0 + q]);
-      } else if (S == 1) {
-        diag_alive<R, S>(C, L, cn, vx[q], (R)0, (R)0);
-      }
+      candmask |= 1 << q;
+    } else if (S == 0) {
+      if (cn == C.cmid) diag_alive<R, S>(C, L.G, cn, vx[q], st.vy[s0 + q], st.vz[s0 + q]);
+    } else if (S == 1) {
+      diag_alive<R, S>(C, L.G, cn, vx[q], (R)0, (R)0);
     }
   }
   if (full) {
@@ -790,22 +864,38 @@ __device__ void push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, in
       }
     }
   }
-  __threadfence_block();
+  // candidates go to this tile's own region of the list: a wave prefix sum
+  // and one LDS atomic per wave, no global atomics
+  const int mine = __popc(candmask);
+  int incl = mine;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  const int wtot = __shfl(incl, 63);
+  int wbase = 0;
+  if (lane == 63 && wtot > 0) wbase = atomicAdd(&L.ncand, wtot);
+  wbase = __shfl(wbase, 63);
+  int pos = wbase + incl - mine;
+  int32_t* region = D.cand[S] + t0;
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+    if (candmask & (1 << q)) region[pos++] = (int32_t)(s0 + q);
   __syncthreads();
-  const int qn = L.qn;
-  for (int k = tid; k < qn; k += TPB) candidate<R, S>(C, D, L, L.q[k], n, base);
-  __syncthreads();
+  if (tid == 0) D.tcnt[S][t0 / TILE] = L.ncand;
   int32_t* cnt_s = D.cnt + (size_t)S * N;
   int64_t* F_s = D.F + (size_t)S * N;
   for (int i = tid; i < WIN; i += TPB) {
-    uint64_t v = L.win[i];
+    const uint64_t v = L.win[i];
     if (v) {
-      int cc = base + i;
+      const int cc = base + i;
       atomicAdd(&cnt_s[cc], (int)(v >> 40));
       atomicAdd((unsigned long long*)&F_s[cc], (unsigned long long)(v & F_MASK));
     }
   }
   __syncthreads();
+  return tc;
 }
 
 template <class R>
@@ -827,14 +917,7 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   const int64_t nstep = D.ctr->step;
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
-  for (int i = tid; i < EEDF_MAX + 1; i += TPB) L.eedf[i] = 0;
-  for (int i = tid; i < FNEG_MAX; i += TPB) L.fneg[i] = 0;
-  if (tid < NCH) L.ev[tid] = 0;
-  if (tid < 6) L.absorbed[tid] = 0;
-  if (tid == 0) {
-    L.tophits = 0;
-    L.psteps = 0;
-  }
+  diag_init(L.G);
   __syncthreads();
   int64_t Ns[3], nt[3];
   double pm[3];
@@ -843,35 +926,35 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
     Ns[s] = (s == 0 || ion) ? D.N[s] : 0;
     nt[s] = (Ns[s] + TILE - 1) / TILE;
     pm[s] = pmax_of(C, D, s);
-    double t = ceil(pm[s] * 4294967296.0);
+    const double t = ceil(pm[s] * 4294967296.0);
     T0[s] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
     if (Ns[s] > 0 && pm[s] > 1.0 && blockIdx.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
   }
   const int64_t total = nt[0] + nt[1] + nt[2];
-  int my_abs[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-  int my_ps = 0;
+  int ps = 0, ae0 = 0, ae1 = 0, an0 = 0, an1 = 0, ap0 = 0, ap1 = 0;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    if (t < nt[0]) push_tile<R, 0>(C, D, L, t * TILE, Ns[0], n, T0[0], pm[0], my_abs[0], &my_ps);
-    else if (t < nt[0] + nt[1]) push_tile<R, 1>(C, D, L, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1], my_abs[1], &my_ps);
-    else push_tile<R, 2>(C, D, L, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2], my_abs[2], &my_ps);
+    if (t < nt[0]) {
+      const TileCount k = push_tile<R, 0>(C, D, L, t * TILE, Ns[0], n, T0[0], pm[0]);
+      ps += k.pushed; ae0 += k.abs0; ae1 += k.abs1;
+    } else if (t < nt[0] + nt[1]) {
+      const TileCount k = push_tile<R, 1>(C, D, L, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
+      ps += k.pushed; an0 += k.abs0; an1 += k.abs1;
+    } else {
+      const TileCount k = push_tile<R, 2>(C, D, L, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
+      ps += k.pushed; ap0 += k.abs0; ap1 += k.abs1;
+    }
   }
-  for (int sp = 0; sp < 3; sp++)
-    for (int side = 0; side < 2; side++)
-      if (my_abs[sp][side]) atomicAdd(&L.absorbed[side * 3 + sp], my_abs[sp][side]);
-  if (my_ps) atomicAdd(&L.psteps, my_ps);
+  // [electrode][species]
+  if (ae0) atomicAdd(&L.G.absorbed[0], ae0);
+  if (an0) atomicAdd(&L.G.absorbed[1], an0);
+  if (ap0) atomicAdd(&L.G.absorbed[2], ap0);
+  if (ae1) atomicAdd(&L.G.absorbed[3], ae1);
+  if (an1) atomicAdd(&L.G.absorbed[4], an1);
+  if (ap1) atomicAdd(&L.G.absorbed[5], ap1);
+  if (ps) atomicAdd(&L.G.psteps, ps);
   __syncthreads();
-  if (tid < 6 && L.absorbed[tid]) atomicAdd((unsigned long long*)&D.ctr->absorbed[tid], (unsigned long long)L.absorbed[tid]);
-  if (tid == 0 && L.psteps) atomicAdd((unsigned long long*)&D.ctr->psteps, (unsigned long long)L.psteps);
-  if (tid < NCH && L.ev[tid]) atomicAdd((unsigned long long*)&D.ctr->events[tid], (unsigned long long)L.ev[tid]);
-  if (tid == 0 && L.tophits) atomicAdd((unsigned long long*)&D.ctr->tophits, (unsigned long long)L.tophits);
-  if (C.eedf_bins > 0)
-    for (int i = tid; i <= C.eedf_bins; i += TPB)
-      if (L.eedf[i]) atomicAdd((unsigned long long*)&D.eedf_acc[i], (unsigned long long)L.eedf[i]);
-  const int nf = C.fneg_xbins * C.fneg_ebins;
-  for (int i = tid; i < nf; i += TPB)
-    if (L.fneg[i]) atomicAdd((unsigned long long*)&D.fneg_acc[i], (unsigned long long)L.fneg[i]);
+  diag_flush(C, D, L.G);
 }
-
 
 // ---------------------------------------------------------------------------
 // last-workgroup detection (no spinning: the final workgroup to arrive does
@@ -1237,13 +1320,15 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
 }
 
 constexpr int SORT_TPB = 256;
-constexpr int SORT_PER = 16;
+constexpr int SORT_PER = 8;
 constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
 constexpr int SORT_WIN = 1024;
 
-// Each workgroup moves one contiguous chunk of a store: ranks inside the chunk
-// come from LDS counters over a window of cells, and one global atomic per
-// (chunk, cell) reserves the destination range.
+// Each workgroup moves one contiguous chunk of a store.  All fields of the
+// chunk are loaded before the ranking.  Inside a wave the lanes of equal cell
+// get consecutive destinations; one LDS atomic per (wave, cell) orders the
+// waves, one global atomic per (chunk, cell) reserves the destination range,
+// so loads and stores are coalesced.
 template <class R>
 __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D) {
   __shared__ int32_t lcnt[SORT_WIN];
@@ -1251,6 +1336,8 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
   __shared__ int32_t wbase;
   const int N = C.N;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const uint64_t below = (1ull << lane) - 1;
   int64_t Ns[3], nch[3];
   for (int s = 0; s < 3; s++) {
     Ns[s] = D.N[s];
@@ -1277,17 +1364,42 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       wbase = (cf == DEAD ? 0 : cf) - 64;
     }
     for (int i = tid; i < SORT_WIN; i += SORT_TPB) lcnt[i] = 0;
-    __syncthreads();
-    const int base = wbase;
     int32_t cell[SORT_PER], rank[SORT_PER];
+    R off[SORT_PER], vx[SORT_PER], vy[SORT_PER], vz[SORT_PER];
+    uint64_t id[SORT_PER];
 #pragma unroll
     for (int j = 0; j < SORT_PER; j++) {
       const int64_t slot = c0 + (int64_t)j * SORT_TPB + tid;
-      cell[j] = slot < Ns[s] ? a.cell[slot] : DEAD;
+      const bool in = slot < Ns[s];
+      cell[j] = in ? a.cell[slot] : DEAD;
+      off[j] = in ? a.off[slot] : (R)0;
+      vx[j] = in ? a.vx[slot] : (R)0;
+      vy[j] = in ? a.vy[slot] : (R)0;
+      vz[j] = in ? a.vz[slot] : (R)0;
+      id[j] = in ? a.id[slot] : 0;
+    }
+    __syncthreads();
+    const int base = wbase;
+#pragma unroll
+    for (int j = 0; j < SORT_PER; j++) {
+      const bool alive = cell[j] != DEAD;
+      const int key = alive ? cell[j] : -1;
       rank[j] = -1;
-      if (cell[j] != DEAD) {
-        const int idx = cell[j] - base;
-        if ((unsigned)idx < (unsigned)SORT_WIN) rank[j] = atomicAdd(&lcnt[idx], 1);
+      uint64_t pending = __ballot(alive);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lkey = __shfl(key, leader);
+        const uint64_t peers = __ballot(key == lkey);
+        const int cnt = __popcll(peers);
+        int gb = 0;
+        if (lane == leader) {
+          const int idx = lkey - base;
+          // window cells: LDS offset (made global below); others: global offset now
+          gb = ((unsigned)idx < (unsigned)SORT_WIN) ? atomicAdd(&lcnt[idx], cnt) : (atomicAdd(&cur[lkey], cnt) | (1 << 30));
+        }
+        gb = __shfl(gb, leader);
+        if (key == lkey) rank[j] = gb + __popcll(peers & below);
+        pending &= ~peers;
       }
     }
     __syncthreads();
@@ -1297,18 +1409,18 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
 #pragma unroll
     for (int j = 0; j < SORT_PER; j++) {
       if (cell[j] == DEAD) continue;
-      const int64_t slot = c0 + (int64_t)j * SORT_TPB + tid;
-      const int32_t dst = rank[j] >= 0 ? lbase[cell[j] - base] + rank[j] : atomicAdd(&cur[cell[j]], 1);
+      const int idx = cell[j] - base;
+      const int32_t dst = ((unsigned)idx < (unsigned)SORT_WIN) ? lbase[idx] + rank[j] : (rank[j] & ~(1 << 30));
       if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1]) {
         atomicOr(&D.ctr->err, ERR_SORT);
         continue;
       }
       b.cell[dst] = cell[j];
-      b.off[dst] = a.off[slot];
-      b.vx[dst] = a.vx[slot];
-      b.vy[dst] = a.vy[slot];
-      b.vz[dst] = a.vz[slot];
-      b.id[dst] = a.id[slot];
+      b.off[dst] = off[j];
+      b.vx[dst] = vx[j];
+      b.vy[dst] = vy[j];
+      b.vz[dst] = vz[j];
+      b.id[dst] = id[j];
     }
     __syncthreads();
   }
