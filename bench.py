@@ -94,13 +94,15 @@ def main():
     avg_launch_s = (push_ms / 1e3) / max(launches, 1)
     bytes_per_launch = bpp * psteps / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    # measured HBM bytes per launch: FETCH_SIZE + WRITE_SIZE counters of the same
+    # kernel (calibrated against a copy of known size), scaled to this run's pushes
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
             t = json.load(open(TRAFFIC_FILE))
             if t.get("workload") == args.workload and t.get("precision") == args.precision:
-                traffic = t.get("bytes_per_launch")
-        except Exception:
+                traffic = round(t["bytes_per_push"] * psteps / max(launches, 1))
+        except (OSError, ValueError, KeyError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

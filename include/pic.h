@@ -137,7 +137,7 @@ int pic_moments(pic_ctx* ctx, pic_moments_t* out);
 int pic_particles(pic_ctx* ctx, int species, int64_t cap, uint64_t* id_host, int32_t* cell_host,
                   double* off_host, double* v_host, int64_t* n_out);
 
-/* Potential and field of the last solve, host [n_cells+1] each (synchronising). */
+/* Potential and field the next step will use, host [n_cells+1] each (synchronising). */
 int pic_field(pic_ctx* ctx, double* phi_host, double* E_host);
 
 /* Node charge of the current alive population, fixed point 2^-24 per macro particle, host [3][n_cells+1]. */

@@ -933,7 +933,11 @@ int64_t or_particles(const or_ctx* c, int sp, int64_t cap, uint64_t* id, int32_t
   return k;
 }
 
+/* the field the next step will use: solved from the current particles */
 void or_field(const or_ctx* c, double* phi, double* E) {
+  or_ctx* m = (or_ctx*)c;
+  deposit_all(m);
+  solve(m, m->Udrive[m->step % m->P.steps_per_period]);
   memcpy(phi, c->phi, sizeof(double) * (size_t)(c->N + 1));
   memcpy(E, c->E, sizeof(double) * (size_t)(c->N + 1));
 }

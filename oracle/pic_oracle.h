@@ -58,7 +58,7 @@ int64_t or_alive(const or_ctx* c, int sp);
 /* alive particles of species sp in store order: id, cell, off, v (3 per particle) */
 int64_t or_particles(const or_ctx* c, int sp, int64_t cap, uint64_t* id, int32_t* cell,
                      double* off, double* v);
-/* the field of the last solve: phi, E at the n_cells+1 nodes */
+/* the field the next step will use (solved from the current particles), n_cells+1 nodes */
 void or_field(const or_ctx* c, double* phi, double* E);
 /* Q (fixed point 2^-24) of the current alive population, [3][n_cells+1] */
 void or_charge(const or_ctx* c, int64_t* Q);

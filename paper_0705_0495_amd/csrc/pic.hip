@@ -3,12 +3,11 @@
 // The host computes the constants of a discharge once (in double, rounded
 // once to the particle precision), owns the device memory and enqueues the
 // kernels of each step on one HIP stream:
-//   k_field    field solve + diagnostics              (1 workgroup)
 //   k_push     fused gather/push/absorb/null test/deposit (persistent grid)
 //   k_collide  collisions of the null-test candidates (persistent grid)
-//   k_tail     partner reactions + bucketing of births (1 workgroup)
-//   k_births   canonical ids, append, close the step  (small grid)
-//   k_sort_*   every sort_every steps
+//   k_serial   partner reactions, births, closing the step and the field
+//              solve of the next step (1 workgroup)
+//   k_sort_*   every sort_every steps, followed by k_field
 // Nothing in a step waits for the host.
 #include "pic.h"
 
@@ -270,6 +269,7 @@ struct Impl : Base {
     if ((rc = alloc(&D.req, (size_t)D.req_cap))) return rc;
     if ((rc = alloc(&D.nreq, 1))) return rc;
     if ((rc = alloc(&D.ctr, 1))) return rc;
+    if ((rc = alloc(&D.Qcur, 3 * (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.Qacc, 3 * (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.Qlast, 3 * (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.phiacc, (size_t)N + 1))) return rc;
@@ -320,6 +320,8 @@ struct Impl : Base {
     }
     HIPCHK(c, hipGetLastError());
     if ((rc = sort())) return rc;
+    // field, diagnostics and accumulator clearing of step 0
+    HIPCHK(c, launch_field(C, D, 1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int32_t e;
     if ((rc = read_err(&e))) return rc;
@@ -339,7 +341,6 @@ struct Impl : Base {
   int step(int64_t nsteps) override {
     const int sort_every = c->G.sort_every;
     for (int64_t k = 0; k < nsteps; k++) {
-      HIPCHK(c, launch_field(C, D, 1, c->stream));
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (c->timing) {
         if (c->ev_used == c->events.size()) {
@@ -356,13 +357,14 @@ struct Impl : Base {
       hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
       hipLaunchKernelGGL(k_collide<R>, dim3(grid_collide), dim3(COLL_TPB), 0, c->stream, C, D);
-      hipLaunchKernelGGL(k_tail<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, C, D);
-      hipLaunchKernelGGL(k_births<R>, dim3(grid_births), dim3(BIRTH_TPB), 0, c->stream, C, D);
       HIPCHK(c, hipGetLastError());
       nstep++;
-      if (nstep % sort_every == 0) {
+      const bool sort_now = (nstep % sort_every) == 0;
+      HIPCHK(c, launch_serial(C, D, sort_now ? 0 : 1, c->stream));
+      if (sort_now) {
         int rc = sort();
         if (rc) return rc;
+        HIPCHK(c, launch_field(C, D, 1, c->stream));
       }
       if (c->timing && c->ev_used >= 16384) {
         int rc = drain_events();
@@ -443,18 +445,8 @@ struct Impl : Base {
 
   int charge(int64_t* Q) override {
     const int N = C.N;
-    std::vector<int32_t> cnt(3 * (size_t)N);
-    std::vector<int64_t> F(3 * (size_t)N);
-    HIPCHK(c, hipMemcpyAsync(cnt.data(), D.cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(F.data(), D.F, sizeof(int64_t) * F.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Q, D.Qcur, sizeof(int64_t) * 3 * (N + 1), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int s = 0; s < 3; s++)
-      for (int i = 0; i <= N; i++) {
-        int64_t v = 0;
-        if (i < N) v += ((int64_t)cnt[s * N + i] << 24) - F[s * N + i];
-        if (i >= 1) v += F[s * N + i - 1];
-        Q[s * (N + 1) + i] = v;
-      }
     return 0;
   }
 
@@ -482,15 +474,15 @@ struct Impl : Base {
     m->particle_steps = h.psteps;
     m->births = h.births;
     m->next_id = h.next_id;
-    // alive counts: between steps the per-cell counts hold exactly the alive particles
+    // alive counts: every alive particle carries 2^24 units of node charge
     {
-      std::vector<int32_t> cnt(3 * (size_t)N);
-      HIPCHK(c, hipMemcpyAsync(cnt.data(), D.cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
+      std::vector<int64_t> Qc(3 * (size_t)(N + 1));
+      int rc = charge(Qc.data());
+      if (rc) return rc;
       for (int s = 0; s < 3; s++) {
         int64_t tot = 0;
-        for (int i = 0; i < N; i++) tot += cnt[(size_t)s * N + i];
-        m->alive[s] = tot;
+        for (int i = 0; i <= N; i++) tot += Qc[(size_t)s * (N + 1) + i];
+        m->alive[s] = tot >> 24;
       }
     }
     const double Mst = (double)c->G.steps_per_period;

@@ -115,6 +115,7 @@ struct Dev {
   Request<R>* req;
   int32_t* nreq;
   Counters* ctr;
+  int64_t* Qcur;    // [3][Nc+1] node charge of the population the next push starts from
   int64_t* Qacc;
   int64_t* Qlast;
   double* phiacc;
@@ -332,14 +333,19 @@ constexpr int FIELD_PER_MAX = (NMAX_CELLS + FIELD_TPB) / FIELD_TPB;
 // accumulators of the species moved in this step).  A single workgroup; each
 // thread owns PER consecutive nodes and issues all of its loads before any
 // dependent arithmetic, so the kernel waits for one memory round trip.
+struct FieldLds {
+  double phis[NMAX_CELLS + 1];
+  __int128 scA[FIELD_TPB];
+  __int128 scB[FIELD_TPB];
+};
+
 template <class R, int PER>
-__global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
-  __shared__ double phis[NMAX_CELLS + 1];
-  __shared__ __int128 scA[FIELD_TPB];
-  __shared__ __int128 scB[FIELD_TPB];
+__device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64_t n, FieldLds& FL) {
+  double* phis = FL.phis;
+  __int128* scA = FL.scA;
+  __int128* scB = FL.scB;
   const int tid = threadIdx.x;
   const int N = C.N;
-  const int64_t n = D.ctr->step;
   const double U = D.U[n % C.M];
   const bool ion = (n % C.nsub) == 0;
   const int i0 = min(tid * PER, N + 1);
@@ -374,6 +380,7 @@ __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int 
       int64_t v = ((int64_t)cn[s][k] << 24) - Fc[s][k];
       v += (k == 0) ? Fp[s] : Fc[s][k - 1];
       Qs[s] = v;
+      D.Qcur[s * (N + 1) + i] = v;
       // one addition per node and step: the order of the sums is fixed
       if (mode == 1) atomicAdd((unsigned long long*)&D.Qacc[s * (N + 1) + i], (unsigned long long)v);
     }
@@ -453,6 +460,12 @@ __global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int 
     if (i >= 1) D.E2[2 * (i - 1) + 1] = er;
     if (mode == 1) D.phiacc[i] = pa[k] + phis[i];
   }
+}
+
+template <class R, int PER>
+__global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
+  __shared__ FieldLds FL;
+  field_phase<R, PER>(C, D, mode, D.ctr->step, FL);
 }
 
 template <class R>
@@ -1138,22 +1151,17 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   if (tid == 0) atomicAdd((unsigned long long*)&D.ctr->nreq, (unsigned long long)nr);
 }
 
+// ---------------------------------------------------------------------------
+// end of step n and start of step n+1, one workgroup of 1024 threads:
+//  1. partner reactions;
+//  2. births: counting sort over creator-id buckets, rank inside the bucket
+//     (canonical ids: rank by creator id, then k), append to the stores;
+//  3. close the step (store lengths, id counter, rf-cycle sums);
+//  4. unless a sort follows, the field of step n+1.
+// ---------------------------------------------------------------------------
 template <class R>
-__global__ void __launch_bounds__(TAIL_TPB) k_tail(Consts<R> C, Dev<R> D) {
-  __shared__ union {
-    ClaimLds claims;
-    int32_t cur[NBUCKET];
-  } U;
-  __shared__ uint64_t bk[TAIL_TPB];
-  __shared__ int32_t bi[TAIL_TPB];
+__device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, int32_t* part) {
   const int tid = threadIdx.x;
-  int nr = *D.nreq;
-  if (nr > D.req_cap) nr = D.req_cap;
-  if (nr > 0) {
-    resolve_claims(C, D, U.claims, bk, bi, nr, (uint32_t)D.ctr->step);
-    __threadfence();
-    __syncthreads();
-  }
   int B = D.nbc[0];
   if (B > D.nb_cap) B = D.nb_cap;
   if (B == 0) return;
@@ -1167,44 +1175,32 @@ __global__ void __launch_bounds__(TAIL_TPB) k_tail(Consts<R> C, Dev<R> D) {
   }
 #pragma unroll
   for (int q = 0; q < PER; q++) D.bhist[tid * PER + q] = 0;
-  bi[tid] = sum;
+  part[tid] = sum;
   __syncthreads();
   for (int d = 1; d < TAIL_TPB; d <<= 1) {
-    const int x = tid >= d ? bi[tid - d] : 0;
+    const int x = tid >= d ? part[tid - d] : 0;
     __syncthreads();
-    bi[tid] += x;
+    part[tid] += x;
     __syncthreads();
   }
-  int run = bi[tid] - sum;
+  int run = part[tid] - sum;
 #pragma unroll
   for (int q = 0; q < PER; q++) {
     D.boff[tid * PER + q] = run;
-    U.cur[tid * PER + q] = run;
+    cur[tid * PER + q] = run;
     run += loc[q];
   }
   if (tid == TAIL_TPB - 1) D.boff[NBUCKET] = run;
   __syncthreads();
-  const uint64_t nid = (uint64_t)D.ctr->next_id;
+  const uint64_t next = (uint64_t)D.ctr->next_id;
   for (int b = tid; b < B; b += TAIL_TPB) {
-    const int bkt = birth_bucket(D.nb[b].creator, nid);
-    const int slot = atomicAdd(&U.cur[bkt], 1);
+    const int bkt = birth_bucket(D.nb[b].creator, next);
+    const int slot = atomicAdd(&cur[bkt], 1);
     D.perm[slot] = b;
   }
-}
-
-// ---------------------------------------------------------------------------
-// births: canonical ids (rank by creator id, then k) inside the creator-id
-// bucket; append to the stores; the last workgroup closes the step
-// ---------------------------------------------------------------------------
-constexpr int BIRTH_TPB = 256;
-
-template <class R>
-__global__ void __launch_bounds__(BIRTH_TPB) k_births(Consts<R> C, Dev<R> D) {
-  const int tid = threadIdx.x;
-  int B = D.nbc[0];
-  if (B > D.nb_cap) B = D.nb_cap;
-  const uint64_t next = (uint64_t)D.ctr->next_id;
-  for (int b = blockIdx.x * BIRTH_TPB + tid; b < B; b += gridDim.x * BIRTH_TPB) {
+  __threadfence();
+  __syncthreads();
+  for (int b = tid; b < B; b += TAIL_TPB) {
     const Birth<R> rec = D.nb[b];
     const uint64_t key = (rec.creator << 2) | (uint64_t)rec.k;
     const int bk = birth_bucket(rec.creator, next);
@@ -1228,10 +1224,33 @@ __global__ void __launch_bounds__(BIRTH_TPB) k_births(Consts<R> C, Dev<R> D) {
       }
     }
   }
-  if (!last_block(&D.done[1])) return;
-  __shared__ int64_t new_step;
+}
+
+template <class R, int PER>
+__global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int do_field) {
+  __shared__ union {
+    FieldLds field;
+    struct {
+      ClaimLds L;
+      uint64_t bk[TAIL_TPB];
+      int32_t bi[TAIL_TPB];
+    } claims;
+    int32_t cur[NBUCKET];
+  } U;
+  __shared__ int32_t part[TAIL_TPB];
+  const int tid = threadIdx.x;
+  const int64_t n = D.ctr->step;
+  int nr = *D.nreq;
+  if (nr > D.req_cap) nr = D.req_cap;
+  if (nr > 0) resolve_claims(C, D, U.claims.L, U.claims.bk, U.claims.bi, nr, (uint32_t)n);
+  __threadfence();
+  __syncthreads();
+  births_phase(C, D, U.cur, part);
+  __threadfence();
+  __syncthreads();
+  int B = D.nbc[0];
+  if (B > D.nb_cap) B = D.nb_cap;
   if (tid == 0) {
-    D.done[1] = 0;
     for (int s = 0; s < 3; s++) {
       int64_t nn = D.N[s] + D.nbc[1 + s];
       if (nn > D.cap[s]) {
@@ -1246,31 +1265,48 @@ __global__ void __launch_bounds__(BIRTH_TPB) k_births(Consts<R> C, Dev<R> D) {
     if ((uint64_t)D.ctr->next_id > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
     D.nbc[0] = 0;
     *D.nreq = 0;
-    D.ctr->step += 1;
-    new_step = D.ctr->step;
+    D.ctr->step = n + 1;
   }
-  __syncthreads();
   // close the rf cycle: move the accumulated sums to the last-cycle buffers
-  if (new_step % C.M == 0) {
+  if ((n + 1) % C.M == 0) {
     const int N = C.N;
-    for (int i = tid; i < 3 * (N + 1); i += BIRTH_TPB) {
+    for (int i = tid; i < 3 * (N + 1); i += TAIL_TPB) {
       D.Qlast[i] = D.Qacc[i];
       D.Qacc[i] = 0;
     }
-    for (int i = tid; i <= N; i += BIRTH_TPB) {
+    for (int i = tid; i <= N; i += TAIL_TPB) {
       D.philast[i] = D.phiacc[i];
       D.phiacc[i] = 0;
     }
-    for (int i = tid; i <= C.eedf_bins; i += BIRTH_TPB) {
+    for (int i = tid; i <= C.eedf_bins; i += TAIL_TPB) {
       D.eedf_last[i] = D.eedf_acc[i];
       D.eedf_acc[i] = 0;
     }
-    for (int i = tid; i < C.fneg_xbins * C.fneg_ebins; i += BIRTH_TPB) {
+    for (int i = tid; i < C.fneg_xbins * C.fneg_ebins; i += TAIL_TPB) {
       D.fneg_last[i] = D.fneg_acc[i];
       D.fneg_acc[i] = 0;
     }
     if (tid == 0) D.ctr->cycles += 1;
   }
+  if (!do_field) return;
+  __threadfence();
+  __syncthreads();
+  field_phase<R, PER>(C, D, 1, n + 1, U.field);
+}
+
+template <class R>
+inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_field, hipStream_t st) {
+  const int per = (C.N + 1 + FIELD_TPB - 1) / FIELD_TPB;
+  switch (per) {
+    case 1: hipLaunchKernelGGL((k_serial<R, 1>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 2: hipLaunchKernelGGL((k_serial<R, 2>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 3: hipLaunchKernelGGL((k_serial<R, 3>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 4: hipLaunchKernelGGL((k_serial<R, 4>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 5: hipLaunchKernelGGL((k_serial<R, 5>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 6: case 7: hipLaunchKernelGGL((k_serial<R, 7>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    default: hipLaunchKernelGGL((k_serial<R, FIELD_PER_MAX>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
