@@ -39,7 +39,8 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("voltage_V", C.c_double), ("frequency_Hz", C.c_double),
         ("pressure_Pa", C.c_double), ("T_gas_K", C.c_double), ("metastable_frac", C.c_double),
         ("eedf_bins", C.c_int32), ("eedf_emax_eV", C.c_double), ("fneg_xbins", C.c_int32),
-        ("fneg_ebins", C.c_int32), ("fneg_emax_eV", C.c_double),
+        ("fneg_ebins", C.c_int32), ("fneg_emax_eV", C.c_double), ("coulomb_every", C.c_int32),
+        ("coulomb_log", C.c_double),
     ]
 
 
@@ -74,6 +75,7 @@ def lib(prec: str = "fp32"):
     L.or_solve_field.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, P(C.c_int64),
                                  P(C.c_double), P(C.c_double)]
     L.or_log_enable.argtypes = [C.c_void_p, C.c_int64]
+    L.or_scale_velocities.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
     L.or_log_read.restype = C.c_int64
     L.or_log_read.argtypes = [C.c_void_p, P(C.c_double), C.c_int64]
     _loaded[prec] = L
@@ -106,7 +108,8 @@ class Oracle:
     """One discharge advanced by the CPU oracle."""
 
     def __init__(self, wl, sigma, threshold, loss, precision="fp32", drive_dc=False,
-                 eedf_bins=128, eedf_emax_eV=64.0, fneg_xbins=32, fneg_ebins=64, fneg_emax_eV=8.0):
+                 eedf_bins=128, eedf_emax_eV=64.0, fneg_xbins=32, fneg_ebins=64, fneg_emax_eV=8.0,
+                 coulomb_every=None):
         self.L = lib(precision)
         self.wl = wl
         p = Params()
@@ -132,6 +135,8 @@ class Oracle:
         p.fneg_xbins = fneg_xbins
         p.fneg_ebins = fneg_ebins
         p.fneg_emax_eV = fneg_emax_eV
+        p.coulomb_every = wl.coulomb_every if coulomb_every is None else coulomb_every
+        p.coulomb_log = wl.coulomb_log
         self.params = p
         self.eedf_bins = eedf_bins
         self.nf = fneg_xbins * fneg_ebins
@@ -211,6 +216,10 @@ class Oracle:
 
     def sigma(self, chan, E):
         return self.L.or_sigma(self.h, chan, E)
+
+    def scale_velocities(self, sp, f):
+        a = np.ascontiguousarray(f, dtype=np.float64)
+        self.L.or_scale_velocities(self.h, sp, _ptr(a, C.c_double))
 
     def log_enable(self, cap):
         self.L.or_log_enable(self.h, cap)

@@ -64,6 +64,7 @@ static const double EPS0 = 8.8541878128e-12;
 static const double ME = 9.1093837015e-31;
 static const double AMU = 1.66053906660e-27;
 static const double TWO_PI = 6.283185307179586;
+static const double PI = 3.141592653589793;
 
 /* ----------------------------------------------------------------------- */
 /* Philox4x32-10                                                            */
@@ -173,6 +174,7 @@ struct or_ctx {
   double PGtot[3];
   double KP[NCH];        /* tau * M_j / (A dx) for partner channels */
   double cphi, cE;
+  real cc_coul[3], cc_coul_half[3]; /* Eq. (2) prefactor per particle in the cell */
   double* Udrive;        /* [M] */
   /* state */
   store st[3];
@@ -377,7 +379,8 @@ static double pmax_of(const or_ctx* c, int s) {
 or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, const double* loss, int* err) {
   *err = OR_OK;
   if (p->n_cells < 4 || p->gap_m <= 0 || p->area_m2 <= 0 || p->weight <= 0 || p->steps_per_period < 1 ||
-      p->ion_subcycle < 1 || p->sort_every < 1 || p->frequency_Hz <= 0) {
+      p->ion_subcycle < 1 || p->sort_every < 1 || p->frequency_Hz <= 0 || p->coulomb_every < 0 ||
+      (p->coulomb_every > 0 && (p->coulomb_every % p->sort_every != 0 || !(p->coulomb_log > 0)))) {
     *err = OR_EINVAL;
     return NULL;
   }
@@ -463,6 +466,16 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
     c->PGtot[SP_E] = c->PG[0] * c->M_gas[SP_E];
     c->PGtot[SP_N] = c->PG[14] * c->M_gas[SP_N] + c->PG[16] * c->M_ad;
     c->PGtot[SP_P] = c->PG[18] * c->M_gas[SP_P];
+  }
+  /* Eq. (2) with eps0^2 (Takizuka-Abe): <tan^2(chi/2)> = q^4 n lnL t_c2 / (8 pi eps0^2 mu^2 u^3),
+     mu = m/2, n = W N_cell / (A dx), t_c2 = coulomb_every dt */
+  for (int s = 0; s < 3; s++) {
+    double mu = 0.5 * c->mass[s];
+    double tc2 = c->dt * (double)(p->coulomb_every > 0 ? p->coulomb_every : 1);
+    double num = ((((QE * QE) * (QE * QE)) * p->coulomb_log) * tc2) * p->weight;
+    double den = (((8.0 * PI) * (EPS0 * EPS0)) * (mu * mu)) * (p->area_m2 * c->dx);
+    c->cc_coul[s] = (real)(num / den);
+    c->cc_coul_half[s] = (real)((0.5 * num) / den);
   }
   c->cphi = ((c->dx * QE) * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
   c->cE = (QE * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
@@ -563,6 +576,10 @@ static double ke(double m, const real v[3]) {
   return 0.5 * m * ((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
 }
 
+/* event log entry (16 doubles): chan, species, kinetic energy before/after, momentum
+   before[3]/after[3], loss, aux0, aux1.  Coulomb collisions log chan = 100 and
+   per unit mass: e[2..9] as above, e[11] the Eq. (2) variance, e[12] the realised
+   tan^2(chi/2), e[13] u, e[14] the cell's particle count, e[15] 1 in a triangle */
 static void log_event(or_ctx* c, int chan, int sp, double keb, double kea, const double pb[3],
                       const double pa[3], double aux0, double aux1) {
   if (!c->log || c->nlog >= c->caplog) return;
@@ -829,6 +846,133 @@ static void claims(or_ctx* c, uint32_t n) {
   }
 }
 
+/* ----------------------------------------------------------------------- */
+/* intra-species Coulomb collisions (1)-(3): binary model of Takizuka and  */
+/* Abe with a Gaussian tan(chi/2) of variance Eq. (2) and uniform azimuth  */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  uint32_t h;
+  uint64_t id;
+  int64_t idx;
+} ckey;
+
+static int ckey_cmp(const void* x, const void* y) {
+  const ckey* a = (const ckey*)x;
+  const ckey* b = (const ckey*)y;
+  if (a->h != b->h) return a->h < b->h ? -1 : 1;
+  if (a->id != b->id) return a->id < b->id ? -1 : 1;
+  return 0;
+}
+
+/* one binary collision of A and B (equal masses); cc = Eq. (2) prefactor times the
+   particle count m of the cell; randoms from Philox(rid, n, k) */
+static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k,
+                       int sp, int64_t m, int half) {
+  real ux = A->v[0] - B->v[0], uy = A->v[1] - B->v[1], uz = A->v[2] - B->v[2];
+  real up2 = ux * ux + uy * uy;
+  real u2 = up2 + uz * uz;
+  if (!(u2 > (real)0)) return;
+  real u = RSQRT(u2);
+  real var = cc / (u2 * u);
+  uint32_t w[4];
+  rng(c->P.seed, rid, n, k, w);
+  real st, omc;
+  if (var > (real)1) { /* deflection too large for the small-angle model: isotropic */
+    real ct = (real)1 - (real)2 * unif(w[3]);
+    st = RSQRT((real)1 - ct * ct);
+    omc = (real)1 - ct;
+  } else {
+    real nrm = bm_radius(unif(w[0])) * cos2pi(unif(w[1]));
+    real d = RSQRT(var) * nrm;
+    real d2 = d * d;
+    real den = (real)1 + d2;
+    st = (d + d) / den;
+    omc = (d2 + d2) / den;
+  }
+  real ph = unif(w[2]);
+  real s1 = st * cos2pi(ph), s2 = st * sin2pi(ph);
+  real du[3];
+  if (up2 > (real)0) {
+    real up = RSQRT(up2);
+    real r = uz * s1, t = u * s2;
+    du[0] = (ux * r - uy * t) / up - ux * omc;
+    du[1] = (uy * r + ux * t) / up - uy * omc;
+    du[2] = -(up * s1) - uz * omc;
+  } else {
+    du[0] = u * s1;
+    du[1] = u * s2;
+    du[2] = -(u * omc);
+  }
+  double pb[3], pa[3], keb = 0, kea = 0;
+  if (c->log) {
+    for (int d = 0; d < 3; d++) pb[d] = (double)A->v[d] + (double)B->v[d];
+    keb = ke(1.0, A->v) + ke(1.0, B->v);
+  }
+  for (int d = 0; d < 3; d++) {
+    real h = (real)0.5 * du[d];
+    A->v[d] = A->v[d] + h;
+    B->v[d] = B->v[d] - h;
+  }
+  if (c->log && c->nlog < c->caplog) {
+    for (int d = 0; d < 3; d++) pa[d] = (double)A->v[d] + (double)B->v[d];
+    kea = ke(1.0, A->v) + ke(1.0, B->v);
+    double vx = (double)A->v[0] - B->v[0], vy = (double)A->v[1] - B->v[1], vz = (double)A->v[2] - B->v[2];
+    double cosx = ((double)ux * vx + (double)uy * vy + (double)uz * vz) /
+                  (sqrt((double)u2) * sqrt(vx * vx + vy * vy + vz * vz));
+    double t2 = (1.0 - cosx) / (1.0 + cosx);
+    double* e = c->log + 16 * c->nlog++;
+    memset(e, 0, 16 * sizeof(double));
+    e[0] = 100; e[1] = sp; e[2] = keb; e[3] = kea;
+    for (int d = 0; d < 3; d++) { e[4 + d] = pb[d]; e[7 + d] = pa[d]; }
+    e[11] = (double)var; e[12] = t2; e[13] = sqrt((double)u2); e[14] = (double)m; e[15] = half;
+  }
+}
+
+static void coulomb(or_ctx* c, uint32_t n) {
+  int N = c->N;
+  for (int s = 0; s < 3; s++) {
+    store* S = &c->st[s];
+    int64_t* start = (int64_t*)calloc((size_t)N + 1, sizeof(int64_t));
+    int64_t nal = 0;
+    for (int64_t i = 0; i < S->n; i++)
+      if (S->a[i].alive) { start[S->a[i].cell + 1]++; nal++; }
+    for (int cc = 0; cc < N; cc++) start[cc + 1] += start[cc];
+    ckey* keys = (ckey*)malloc(sizeof(ckey) * (size_t)(nal > 0 ? nal : 1));
+    int64_t* fill = (int64_t*)calloc((size_t)N, sizeof(int64_t));
+    for (int64_t i = 0; i < S->n; i++) {
+      part* p = &S->a[i];
+      if (!p->alive) continue;
+      uint32_t w[4];
+      rng(c->P.seed, p->id, n, 16, w);
+      ckey* k = &keys[start[p->cell] + fill[p->cell]++];
+      k->h = w[0];
+      k->id = p->id;
+      k->idx = i;
+    }
+    for (int cc = 0; cc < N; cc++) {
+      int64_t m = start[cc + 1] - start[cc];
+      if (m < 2) continue;
+      ckey* K = keys + start[cc];
+      qsort(K, (size_t)m, sizeof(ckey), ckey_cmp);
+      int64_t first = 0;
+      if (m % 2 == 1) {  /* odd: the first three collide pairwise with half the interval */
+        real ch = c->cc_coul_half[s] * (real)m;
+        part *a = &S->a[K[0].idx], *b = &S->a[K[1].idx], *d = &S->a[K[2].idx];
+        ta_collide(c, a, b, ch, K[0].id, n, 17, s, m, 1);
+        ta_collide(c, b, d, ch, K[1].id, n, 18, s, m, 1);
+        ta_collide(c, d, a, ch, K[2].id, n, 19, s, m, 1);
+        first = 3;
+      }
+      real cf = c->cc_coul[s] * (real)m;
+      for (int64_t q = first; q + 1 < m; q += 2)
+        ta_collide(c, &S->a[K[q].idx], &S->a[K[q + 1].idx], cf, K[q].id, n, 17, s, m, 0);
+    }
+    free(start);
+    free(keys);
+    free(fill);
+  }
+}
+
 static int birth_cmp(const void* x, const void* y) {
   const birth* a = (const birth*)x;
   const birth* b = (const birth*)y;
@@ -883,6 +1027,7 @@ static int one_step(or_ctx* c) {
   int rc = commit_births(c);
   if (rc) return rc;
   if ((c->step + 1) % c->P.sort_every == 0) do_sort(c);
+  if (c->P.coulomb_every > 0 && (c->step + 1) % c->P.coulomb_every == 0) coulomb(c, n);
   if ((c->step + 1) % M == 0) {
     memcpy(c->Qlast, c->Qacc, sizeof(int64_t) * 3 * (size_t)(N + 1));
     memcpy(c->philast, c->phiacc, sizeof(double) * (size_t)(N + 1));
@@ -983,6 +1128,12 @@ void or_constants(const or_ctx* c, double* out) {
   out[13] = c->cphi;
   out[14] = c->cE;
   out[15] = (double)c->segmax[SP_P];
+}
+
+void or_scale_velocities(or_ctx* c, int sp, const double f[3]) {
+  store* S = &c->st[sp];
+  for (int64_t i = 0; i < S->n; i++)
+    for (int d = 0; d < 3; d++) S->a[i].v[d] = (real)((double)S->a[i].v[d] * f[d]);
 }
 
 void or_log_enable(or_ctx* c, int64_t cap) {

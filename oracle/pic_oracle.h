@@ -38,6 +38,8 @@ typedef struct {
   double eedf_emax_eV;
   int32_t fneg_xbins, fneg_ebins;
   double fneg_emax_eV;
+  int32_t coulomb_every;      /* intra-species Coulomb collisions every n2 steps, 0 = off */
+  double coulomb_log;         /* ln Lambda */
 } or_params;
 
 typedef struct or_ctx or_ctx;
@@ -76,6 +78,8 @@ double or_sigma(const or_ctx* c, int chan, double E_eV);   /* table interpolatio
 /* Poisson solve of the discrete Dirichlet problem from integer net charge q[0..N] */
 void or_solve_field(int32_t N, double dx, double cphi, double cE, double U0, const int64_t* q,
                     double* phi, double* E);
+/* test hook: multiply velocity component d of every particle of species sp by f[d] */
+void or_scale_velocities(or_ctx* c, int sp, const double f[3]);
 /* event log: enable with capacity; entries of 16 doubles (see source) */
 void or_log_enable(or_ctx* c, int64_t cap);
 int64_t or_log_read(const or_ctx* c, double* out, int64_t cap);

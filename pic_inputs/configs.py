@@ -51,6 +51,8 @@ class Workload:
     T_gas_K: float = 300.0
     metastable_frac: float = 1.0 / 6.0
     sort_every: int = 10
+    coulomb_every: int = 0       # intra-species Coulomb collisions every n2 steps (0: off)
+    coulomb_log: float = 10.0
     seed: int = 705049500
     area_m2: float = field(default_factory=debye_area)
     weight: float = 0.0      # 0 -> n_res * A * L / N_e(0)

@@ -1,0 +1,202 @@
+"""Pins of the oracle's intra-species Coulomb collisions, reactions (1)-(3).
+
+The binary model of Takizuka and Abe (J. Comput. Phys. 25, 205 (1977)) used in
+Sec. III: particles of one species in one cell are paired at random, each pair
+is rotated in its centre-of-mass frame by a scattering angle chi whose
+tan(chi/2) is Gaussian with the variance of Eq. (2) and by a uniform azimuth.
+What is pinned here, independently of the oracle's own arithmetic:
+
+* per pair, momentum and kinetic energy are conserved (equal masses);
+* each particle takes part in exactly one pair per Coulomb step, except that an
+  odd cell starts with a triangle of three pairs at half the variance;
+* the realised tan^2(chi/2) / <tan^2(chi/2)> follows the chi-square law with one
+  degree of freedom (a Gaussian tan(chi/2));
+* the ensemble relaxes a temperature anisotropy at the Landau/Spitzer
+  isotropisation rate of the NRL Plasma Formulary, which fixes the absolute
+  prefactor of Eq. (2) (q^4 n ln(Lambda) t / (8 pi eps0^2 mu^2 u^3), with
+  eps0 squared and the reduced mass mu = m/2 for like particles).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+from oracle.oracle import Oracle
+from pic_inputs.configs import EPS0, QE
+from tests.oracle_helpers import quiet, small, zero_tables
+
+AMU = 1.66053906660e-27
+ME = 9.1093837015e-31
+M_ONEG = 15.999 * AMU + ME
+
+
+def _coulomb_events(log):
+    return log[log[:, 0] == 100]
+
+
+def _cell_pairs(m):
+    """Binary collisions of a cell of m particles: m/2 pairs, or a triangle of
+    three plus (m-3)/2 pairs when m is odd."""
+    if m < 2:
+        return 0
+    if m % 2:
+        return 3 + (m - 3) // 2
+    return m // 2
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_coulomb_pairs_conserve_momentum_and_energy(precision):
+    wl = small(n_init=(3000, 600, 3000), sort_every=5, coulomb_every=5, coulomb_log=10.0)
+    o = Oracle(wl, *zero_tables(), precision=precision)
+    o.log_enable(1 << 16)
+    o.step(5)
+    ev = _coulomb_events(o.log())
+    assert len(ev) > 2000
+    tol = 2e-6 if precision == "fp32" else 1e-14
+    ke_b, ke_a = ev[:, 2], ev[:, 3]
+    assert np.all(np.abs(ke_a - ke_b) <= 4 * tol * ke_b)
+    pb, pa = ev[:, 4:7], ev[:, 7:10]
+    scale = np.sqrt(2 * ke_b)[:, None]
+    assert np.all(np.abs(pa - pb) <= 4 * tol * scale)
+    # every pair scattered (angles of 1e-7 rad are lost to rounding in fp32)
+    if precision == "fp64":
+        assert np.all(ev[:, 12] > 0)
+    o.close()
+
+
+def test_coulomb_pairing_counts_per_cell():
+    wl = small(n_init=(2001, 401, 1999), n_cells=128, sort_every=10, coulomb_every=10)
+    o = Oracle(wl, *zero_tables())
+    o.log_enable(1 << 16)
+    o.step(10)
+    ev = _coulomb_events(o.log())
+    for sp in range(3):
+        _, cell, _, _ = o.particles(sp)
+        counts = np.bincount(cell, minlength=wl.n_cells)
+        want = sum(_cell_pairs(int(m)) for m in counts)
+        es = ev[ev[:, 1] == sp]
+        assert len(es) == want, sp
+        # every logged collision carries its cell's population
+        hist = np.bincount(es[:, 14].astype(int), minlength=counts.max() + 1)
+        want_hist = np.zeros_like(hist)
+        for m in counts:
+            want_hist[m] += _cell_pairs(int(m))
+        assert np.array_equal(hist, want_hist)
+        # triangles exactly in odd cells, three collisions each
+        tri = es[es[:, 15] == 1]
+        assert len(tri) == 3 * int(np.sum((counts % 2 == 1) & (counts >= 3)))
+        assert np.all(es[es[:, 14] % 2 == 0, 15] == 0)
+    o.close()
+
+
+def test_triangle_uses_half_the_variance():
+    wl = small(n_init=(2001, 401, 1999), sort_every=10, coulomb_every=10)
+    o = Oracle(wl, *zero_tables(), precision="fp64")
+    o.log_enable(1 << 16)
+    o.step(10)
+    ev = _coulomb_events(o.log())
+    for sp in range(3):
+        es = ev[ev[:, 1] == sp]
+        # var * u^3 / m is the same constant for every full pair of a species
+        k = es[:, 11] * es[:, 13] ** 3 / es[:, 14]
+        full, half = k[es[:, 15] == 0], k[es[:, 15] == 1]
+        assert len(half) > 0 and len(full) > 0
+        assert np.allclose(full, full[0], rtol=1e-12)
+        assert np.allclose(half, 0.5 * full[0], rtol=1e-12)
+    o.close()
+
+
+def test_tan_half_angle_is_gaussian():
+    # ions with a variance of a few 1e-3: the small-angle branch throughout
+    wl = small(n_init=(0, 40000, 0), T_init_eV=(3.0, 0.026, 0.026), sort_every=1, coulomb_every=1,
+               coulomb_log=10.0)
+    wl = quiet(wl, coulomb_log=1e30)
+    o = Oracle(wl, *zero_tables(), precision="fp64")
+    o.log_enable(1 << 17)
+    o.step(1)
+    ev = _coulomb_events(o.log())
+    ev = ev[ev[:, 11] < 0.05]
+    assert len(ev) > 10000
+    z = ev[:, 12] / ev[:, 11]
+    res = scipy.stats.kstest(z, scipy.stats.chi2(df=1).cdf)
+    assert res.pvalue > 1e-3, res
+    assert abs(np.mean(z) - 1.0) < 0.05
+    o.close()
+
+
+def _nrl_isotropisation_rate(n, lnl, q, m, T_par, T_perp):
+    """nu_T of the NRL Plasma Formulary (temperature isotropisation of one
+    species), in SI units: dT_perp/dt = -nu_T (T_perp - T_par),
+    dT_par/dt = 2 nu_T (T_perp - T_par); T in joules."""
+    A = T_perp / T_par - 1.0
+    if abs(A) < 1e-6:
+        b = 4.0 / 15.0
+    elif A > 0:
+        b = (-3.0 + (A + 3.0) * math.atan(math.sqrt(A)) / math.sqrt(A)) / A**2
+    else:
+        b = (-3.0 + (A + 3.0) * math.atanh(math.sqrt(-A)) / math.sqrt(-A)) / A**2
+    e2 = q * q / (4 * math.pi * EPS0)
+    return 2 * math.sqrt(math.pi) * e2 * e2 * n * lnl / (math.sqrt(m) * T_par**1.5) * b
+
+
+def _relaxation_rate_ratio(precision, nu_dt, steps, n_part=200_000, A0=0.4):
+    """Relax a bi-Maxwellian O- population (T_x = T/(1+A0), T_y = T_z = T) by
+    Coulomb collisions alone and return ln(measured decay of T_perp - T_par)
+    over ln(the decay the NRL rate equations give for the same time)."""
+    wl = quiet(small(n_init=(0, n_part, 0), sort_every=1, coulomb_every=1))
+    dt = 1.0 / (wl.frequency_Hz * wl.steps_per_period)
+    T0 = wl.T_init_eV[1] * QE
+    n = wl.weight * n_part / (wl.area_m2 * wl.gap_m)
+    # ln(Lambda) such that nu_T dt = nu_dt at the start (the tiny weight that
+    # removes the self field is compensated by a huge ln(Lambda))
+    lnl = nu_dt / (dt * _nrl_isotropisation_rate(n, 1.0, QE, M_ONEG, T0, T0))
+    o = Oracle(dataclasses.replace(wl, coulomb_log=lnl), *zero_tables(), precision=precision)
+    o.scale_velocities(1, [1.0 / math.sqrt(1.0 + A0), 1.0, 1.0])
+
+    def temps():
+        _, _, _, v = o.particles(1)
+        t = M_ONEG * np.mean(v * v, axis=0)
+        return t[0], 0.5 * (t[1] + t[2])
+
+    tpar, tperp = temps()
+    o.step(steps)
+    tpar1, tperp1 = temps()
+    o.close()
+    # the collisions conserve the total energy
+    assert abs((tpar1 + 2 * tperp1) / (tpar + 2 * tperp) - 1) < 1e-4
+    y = np.array([tpar, tperp])
+
+    def f(y):
+        nu = _nrl_isotropisation_rate(n, lnl, QE, M_ONEG, y[0], y[1])
+        return np.array([2 * nu * (y[1] - y[0]), -nu * (y[1] - y[0])])
+
+    h = dt / 10
+    for _ in range(steps * 10):  # RK4
+        k1 = f(y)
+        k2 = f(y + 0.5 * h * k1)
+        k3 = f(y + 0.5 * h * k2)
+        k4 = f(y + h * k3)
+        y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    want = (y[1] - y[0]) / (tperp - tpar)
+    got = (tperp1 - tpar1) / (tperp - tpar)
+    assert 0.3 < want < 0.8
+    return math.log(got) / math.log(want)
+
+
+def test_anisotropy_relaxes_at_the_landau_rate():
+    """The binary model reaches the Landau rate only as the collision interval
+    shrinks (a finite Gaussian tan(chi/2) gives <sin^2 chi> < 4 <tan^2(chi/2)>,
+    and pairs with a variance above 1 are scattered isotropically): at
+    nu_T t_c2 = 0.0025 and 0.00125 the rate is a few per cent low, and halving
+    the interval moves it towards the NRL value.  A wrong factor in Eq. (2)
+    (eps0 instead of eps0^2, m instead of mu, a lost 2) misses by 2x or more."""
+    r1 = _relaxation_rate_ratio("fp64", 0.0025, 80)
+    r2 = _relaxation_rate_ratio("fp64", 0.00125, 160)
+    assert 0.88 < r1 < r2 < 1.03, (r1, r2)
+    assert abs((2 * r2 - r1) - 1.0) < 0.05, (r1, r2)
+    r32 = _relaxation_rate_ratio("fp32", 0.0025, 80)
+    assert abs(r32 - r1) < 0.03, (r32, r1)
