@@ -77,6 +77,8 @@ typedef struct {
   int32_t fneg_xbins;         /* O- f(E,x), E = sign(v_x) M v_x^2 / 2; xbins*ebins <= 2048 */
   int32_t fneg_ebins;
   double fneg_emax_eV;
+  int32_t coulomb_every;      /* intra-species Coulomb collisions (1)-(3) every coulomb_every steps
+                                 (n2 = t_c2 / dt of Sec. II); 0 = off; a multiple of sort_every */
 } pic_geometry;
 
 /* Gas and cross sections (Sec. III). */
@@ -86,6 +88,7 @@ typedef struct {
   const double* sigma_m2;     /* host [PIC_NCHAN][PIC_XS_NPOINTS], linear in E between nodes */
   const double* threshold_eV; /* host [PIC_NCHAN], channel closed below */
   const double* loss_eV;      /* host [PIC_NCHAN], excitation energy dE of Eq. (5) */
+  double coulomb_log;         /* ln(Lambda) of Eq. (2); > 0 when coulomb_every > 0 */
 } pic_gas;
 
 /*
@@ -104,8 +107,11 @@ int pic_set_stream(pic_ctx* ctx, void* hip_stream);
 /*
  * Enqueue n_steps time steps (asynchronous).  One step: field solve, push and
  * collisions of every species moved in this step, partner reactions, births
- * and, every sort_every steps, the cell sort.  Guard conditions raised on the
- * device are reported by pic_sync.
+ * and, every sort_every steps, the cell sort, followed every coulomb_every
+ * steps by the intra-species Coulomb collisions of Sec. III (binary model of
+ * Takizuka and Abe, variance of tan(chi/2) from Eq. (2); at most 16384
+ * particles of one species per cell, else PIC_EOVERFLOW).  Guard conditions
+ * raised on the device are reported by pic_sync.
  */
 int pic_step(pic_ctx* ctx, int64_t n_steps);
 

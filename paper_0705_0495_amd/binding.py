@@ -32,7 +32,7 @@ class Geometry(C.Structure):
         ("drive_dc", C.c_int32), ("n_init", C.c_int64 * 3), ("T_init_eV", C.c_double * 3), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("capacity", C.c_int64 * 3), ("eedf_bins", C.c_int32),
         ("eedf_emax_eV", C.c_double), ("fneg_xbins", C.c_int32), ("fneg_ebins", C.c_int32),
-        ("fneg_emax_eV", C.c_double),
+        ("fneg_emax_eV", C.c_double), ("coulomb_every", C.c_int32),
     ]
 
 
@@ -40,6 +40,7 @@ class Gas(C.Structure):
     _fields_ = [
         ("T_gas_K", C.c_double), ("metastable_frac", C.c_double), ("sigma_m2", C.POINTER(C.c_double)),
         ("threshold_eV", C.POINTER(C.c_double)), ("loss_eV", C.POINTER(C.c_double)),
+        ("coulomb_log", C.c_double),
     ]
 
 
@@ -112,6 +113,7 @@ class Discharge:
         g.fneg_xbins = fneg_xbins
         g.fneg_ebins = fneg_ebins
         g.fneg_emax_eV = fneg_emax_eV
+        g.coulomb_every = getattr(wl, "coulomb_every", 0)
         self._sig = np.ascontiguousarray(sigma, dtype=np.float64)
         self._thr = np.ascontiguousarray(threshold, dtype=np.float64)
         self._loss = np.ascontiguousarray(loss, dtype=np.float64)
@@ -121,6 +123,7 @@ class Discharge:
         gas.sigma_m2 = _p(self._sig, C.c_double)
         gas.threshold_eV = _p(self._thr, C.c_double)
         gas.loss_eV = _p(self._loss, C.c_double)
+        gas.coulomb_log = getattr(wl, "coulomb_log", 0.0)
         self.h = C.c_void_p()
         rc = self.L.pic_create(C.byref(g), C.byref(gas), wl.voltage_V, wl.frequency_Hz, wl.pressure_Pa,
                                C.byref(self.h))

@@ -7,7 +7,8 @@
 //   k_collide  collisions of the null-test candidates (persistent grid)
 //   k_serial   partner reactions, births, closing the step and the field
 //              solve of the next step (1 workgroup)
-//   k_sort_*   every sort_every steps, followed by k_field
+//   k_sort_*   every sort_every steps, followed by k_coulomb (every
+//              coulomb_every steps) and k_field
 // Nothing in a step waits for the host.
 #include "pic.h"
 
@@ -112,7 +113,7 @@ struct Impl : Base {
   Consts<R> C;
   Dev<R> D;
   std::vector<void*> allocs;
-  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0;
+  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0, grid_coulomb = 0;
   int64_t nstep = 0;  // steps enqueued
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
@@ -221,6 +222,17 @@ struct Impl : Base {
     C.eedf_sc = (R)(G.eedf_bins > 0 ? (double)G.eedf_bins / G.eedf_emax_eV : 0.0);
     C.fneg_sc = (R)(G.fneg_ebins > 0 ? (double)G.fneg_ebins / (2.0 * G.fneg_emax_eV) : 0.0);
     C.fneg_em = (R)G.fneg_emax_eV;
+    // Eq. (2) with eps0^2 and the reduced mass mu = m/2 of like particles; the
+    // density is W * (particles in the cell) / (A dx), t_c2 = coulomb_every dt
+    const double PI_H = 3.141592653589793;
+    for (int s = 0; s < 3; s++) {
+      const double mu = 0.5 * mass[s];
+      const double tc2 = dt * (double)(G.coulomb_every > 0 ? G.coulomb_every : 1);
+      const double num = ((((QE * QE) * (QE * QE)) * c->gas.coulomb_log) * tc2) * G.weight;
+      const double den = (((8.0 * PI_H) * (EPS0 * EPS0)) * (mu * mu)) * (G.area_m2 * dx);
+      C.ccoul[s] = (R)(num / den);
+      C.ccoul_h[s] = (R)((0.5 * num) / den);
+    }
   }
 
   int create() override {
@@ -303,6 +315,7 @@ struct Impl : Base {
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
     grid_scatter = std::max(1, ncu * 4);
     grid_collide = std::max(1, ncu * 8);
+    grid_coulomb = 3 * N;  // one workgroup per (species, cell); 147 KB of LDS each
 
     // initial load, deposit, field at t = 0, half step back, first sort
     const int64_t tot = G.n_init[0] + G.n_init[1] + G.n_init[2];
@@ -364,6 +377,12 @@ struct Impl : Base {
       if (sort_now) {
         int rc = sort();
         if (rc) return rc;
+        const int ce = c->G.coulomb_every;
+        if (ce > 0 && nstep % ce == 0) {
+          hipLaunchKernelGGL(k_coulomb<R>, dim3(grid_coulomb), dim3(COUL_TPB), 0, c->stream, C, D,
+                             (uint32_t)(nstep - 1));
+          HIPCHK(c, hipGetLastError());
+        }
         HIPCHK(c, launch_field(C, D, 1, c->stream));
       }
       if (c->timing && c->ev_used >= 16384) {
@@ -391,7 +410,7 @@ struct Impl : Base {
     HIPCHK(c, hipMemcpyAsync(&h, D.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *e = h.err;
-    if (h.err & (ERR_CAP | ERR_NB | ERR_REQ | ERR_ID | ERR_SORT))
+    if (h.err & (ERR_CAP | ERR_NB | ERR_REQ | ERR_ID | ERR_SORT | ERR_COUL))
       return fail(c, PIC_EOVERFLOW, "device reported capacity overflow (flags " + std::to_string(h.err) + ")");
     if (h.err & (ERR_PMAX | ERR_NAN))
       return fail(c, PIC_EGUARD, "device guard raised (flags " + std::to_string(h.err) + ")");
@@ -513,7 +532,8 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       !(pressure_Pa >= 0) || !(gas->T_gas_K > 0) || g->precision < 0 || g->precision > 1 || g->eedf_bins < 0 ||
       g->eedf_bins > EEDF_MAX || g->fneg_xbins < 0 || g->fneg_ebins < 0 ||
       (int64_t)g->fneg_xbins * g->fneg_ebins > FNEG_MAX || (g->eedf_bins > 0 && !(g->eedf_emax_eV > 0)) ||
-      (g->fneg_ebins > 0 && !(g->fneg_emax_eV > 0)))
+      (g->fneg_ebins > 0 && !(g->fneg_emax_eV > 0)) || g->coulomb_every < 0 ||
+      (g->coulomb_every > 0 && (g->coulomb_every % g->sort_every != 0 || !(gas->coulomb_log > 0))))
     return PIC_EINVAL;
   for (int s = 0; s < 3; s++)
     if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 31) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;

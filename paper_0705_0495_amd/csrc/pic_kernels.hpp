@@ -31,7 +31,8 @@ constexpr uint64_t ID_MASK = (1ull << 40) - 1;
 constexpr uint64_t F_MASK = (1ull << 40) - 1;
 constexpr double TWO_PI = 6.283185307179586;
 
-enum : int32_t { ERR_PMAX = 1, ERR_CAP = 2, ERR_NB = 4, ERR_REQ = 8, ERR_ID = 16, ERR_NAN = 32, ERR_SORT = 64 };
+enum : int32_t { ERR_PMAX = 1, ERR_CAP = 2, ERR_NB = 4, ERR_REQ = 8, ERR_ID = 16, ERR_NAN = 32, ERR_SORT = 64,
+                    ERR_COUL = 128 };
 
 // constants of one discharge (computed once on the host, rounded once to R)
 template <class R>
@@ -50,6 +51,7 @@ struct Consts {
   double cphi, cE, invdx, inv2dx;
   int32_t eedf_bins, fneg_xbins, fneg_ebins, pad;
   R eedf_sc, fneg_sc, fneg_em;
+  R ccoul[3], ccoul_h[3];   // Eq. (2) prefactor per particle in the cell: full and half interval
 };
 
 struct Counters {
@@ -1464,6 +1466,192 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
   if (threadIdx.x == 0) {
     D.done[2] = 0;
     for (int s = 0; s < 3; s++) D.N[s] = D.Nnew[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// intra-species Coulomb collisions (1)-(3): binary model of Takizuka and Abe
+// with a Gaussian tan(chi/2) of the Eq. (2) variance and a uniform azimuth,
+// run right after a sort, when each cell's particles are one segment
+// ---------------------------------------------------------------------------
+constexpr int COUL_TPB = 1024;
+constexpr int COUL_MAXC = 16384;                 // particles of one species in one cell
+constexpr int COUL_NB = COUL_MAXC / 4;           // buckets of the pairing order
+
+// one collision of two equal-mass particles; cc = prefactor times the cell count
+template <class R>
+__device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R cc, uint64_t rid, uint32_t n,
+                                        uint32_t k) {
+  const R ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
+  const R up2 = ux * ux + uy * uy;
+  const R u2 = up2 + uz * uz;
+  if (!(u2 > (R)0)) return;
+  const R u = Sqrt(u2);
+  const R var = cc / (u2 * u);
+  const uint4 w = rng(C, rid, n, k);
+  R st, omc;
+  if (var > (R)1) {  // beyond the small-angle model: isotropic
+    const R ct = (R)1 - (R)2 * unif<R>(w.w);
+    st = Sqrt((R)1 - ct * ct);
+    omc = (R)1 - ct;
+  } else {
+    const R nrm = bm_radius<R>(unif<R>(w.x)) * cos2pi<R>(unif<R>(w.y));
+    const R d = Sqrt(var) * nrm;
+    const R d2 = d * d;
+    const R den = (R)1 + d2;
+    st = (d + d) / den;
+    omc = (d2 + d2) / den;
+  }
+  const R ph = unif<R>(w.z);
+  const R s1 = st * cos2pi<R>(ph), s2 = st * sin2pi<R>(ph);
+  R du[3];
+  if (up2 > (R)0) {
+    const R up = Sqrt(up2);
+    const R r = uz * s1, t = u * s2;
+    du[0] = (ux * r - uy * t) / up - ux * omc;
+    du[1] = (uy * r + ux * t) / up - uy * omc;
+    du[2] = -(up * s1) - uz * omc;
+  } else {
+    du[0] = u * s1;
+    du[1] = u * s2;
+    du[2] = -(u * omc);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const R h = (R)0.5 * du[d];
+    va[d] = va[d] + h;
+    vb[d] = vb[d] - h;
+  }
+}
+
+// exclusive prefix sum of a[0..n) in LDS by one 1024-thread workgroup
+__device__ inline void block_scan_excl(int32_t* a, int n, int32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int per = (n + COUL_TPB - 1) / COUL_TPB;
+  const int i0 = min(tid * per, n), i1 = min(i0 + per, n);
+  int32_t loc = 0;
+  for (int i = i0; i < i1; i++) loc += a[i];
+  int32_t x = loc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  if (tid < 64) {
+    int32_t z = tid < COUL_TPB / 64 ? wsum[tid] : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(z, d);
+      if (lane >= d) z += y;
+    }
+    if (tid < COUL_TPB / 64) wsum[tid] = z;
+  }
+  __syncthreads();
+  int32_t run = x - loc + (wv > 0 ? wsum[wv - 1] : 0);
+  for (int i = i0; i < i1; i++) {
+    const int32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+}
+
+struct CoulLds {
+  uint32_t h[COUL_MAXC];     // pairing hash by segment position
+  uint16_t list[COUL_MAXC];  // positions grouped by bucket
+  uint16_t ord[COUL_MAXC];   // positions in pairing order
+  int32_t bend[COUL_NB];     // bucket starts, then bucket ends
+  int32_t wsum[COUL_TPB / 64];
+};
+
+__device__ __forceinline__ int coul_bucket(uint32_t h, int nb) { return (int)(((uint64_t)h * (uint32_t)nb) >> 32); }
+
+// One workgroup per (species, cell) segment at a time.  The pairing order is
+// the particles sorted by (Philox(id, n, 16).x, id): a counting sort into
+// nb = ceil(m/4) buckets on the hash (monotone in it), then each particle's
+// rank is its bucket start plus the members of its bucket that precede it.
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
+  __shared__ CoulLds L;
+  const int N = C.N;
+  const int tid = threadIdx.x;
+  for (int w = blockIdx.x; w < 3 * N; w += gridDim.x) {
+    const int s = w / N, cell = w - s * N;
+    const int32_t a = D.seg[s * (N + 1) + cell];
+    const int m = D.seg[s * (N + 1) + cell + 1] - a;
+    if (m < 2) continue;
+    if (m > COUL_MAXC) {
+      if (tid == 0) atomicOr(&D.ctr->err, ERR_COUL);
+      continue;
+    }
+    const Store<R> S = D.st[s];
+    const int nb = (m + 3) >> 2;
+    for (int i = tid; i < nb; i += COUL_TPB) L.bend[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += COUL_TPB) {
+      const uint32_t h = rng(C, S.id[a + i], n, 16).x;
+      L.h[i] = h;
+      atomicAdd(&L.bend[coul_bucket(h, nb)], 1);
+    }
+    __syncthreads();
+    block_scan_excl(L.bend, nb, L.wsum);
+    for (int i = tid; i < m; i += COUL_TPB) {
+      const int pos = atomicAdd(&L.bend[coul_bucket(L.h[i], nb)], 1);
+      L.list[pos] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += COUL_TPB) {
+      const uint32_t hi = L.h[i];
+      const int b = coul_bucket(hi, nb);
+      const int b0 = b > 0 ? L.bend[b - 1] : 0, b1 = L.bend[b];
+      int r = b0;
+      for (int k = b0; k < b1; k++) {
+        const int j = L.list[k];
+        const uint32_t hj = L.h[j];
+        if (hj < hi || (hj == hi && j != i && S.id[a + j] < S.id[a + i])) r++;
+      }
+      L.ord[r] = (uint16_t)i;
+    }
+    __syncthreads();
+    // pairs (o[q], o[q+1]); an odd cell first runs the triangle (o0,o1), (o1,o2),
+    // (o2,o0) with half the interval, in that order, on one thread
+    const int first = (m & 1) ? 3 : 0;
+    const int npairs = (m - first) >> 1;
+    const R cf = C.ccoul[s] * (R)m;
+    for (int p = tid; p < npairs + (first ? 1 : 0); p += COUL_TPB) {
+      if (first && p == npairs) {
+        const R ch = C.ccoul_h[s] * (R)m;
+        if (L.ord[0] >= m || L.ord[1] >= m || L.ord[2] >= m) {
+          atomicOr(&D.ctr->err, ERR_COUL);
+          continue;
+        }
+        const int i0 = a + L.ord[0], i1 = a + L.ord[1], i2 = a + L.ord[2];
+        R v0[3] = {S.vx[i0], S.vy[i0], S.vz[i0]};
+        R v1[3] = {S.vx[i1], S.vy[i1], S.vz[i1]};
+        R v2[3] = {S.vx[i2], S.vy[i2], S.vz[i2]};
+        ta_pair<R>(C, v0, v1, ch, S.id[i0], n, 17);
+        ta_pair<R>(C, v1, v2, ch, S.id[i1], n, 18);
+        ta_pair<R>(C, v2, v0, ch, S.id[i2], n, 19);
+        S.vx[i0] = v0[0]; S.vy[i0] = v0[1]; S.vz[i0] = v0[2];
+        S.vx[i1] = v1[0]; S.vy[i1] = v1[1]; S.vz[i1] = v1[2];
+        S.vx[i2] = v2[0]; S.vy[i2] = v2[1]; S.vz[i2] = v2[2];
+        continue;
+      }
+      const int q = first + 2 * p;
+      if (L.ord[q] >= m || L.ord[q + 1] >= m) {  // not a permutation: ids were not unique
+        atomicOr(&D.ctr->err, ERR_COUL);
+        continue;
+      }
+      const int ia = a + L.ord[q], ib = a + L.ord[q + 1];
+      R va[3] = {S.vx[ia], S.vy[ia], S.vz[ia]};
+      R vb[3] = {S.vx[ib], S.vy[ib], S.vz[ib]};
+      ta_pair<R>(C, va, vb, cf, S.id[ia], n, 17);
+      S.vx[ia] = va[0]; S.vy[ia] = va[1]; S.vz[ia] = va[2];
+      S.vx[ib] = vb[0]; S.vy[ib] = vb[1]; S.vz[ib] = vb[2];
+    }
+    __syncthreads();
   }
 }
 

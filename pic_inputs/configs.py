@@ -18,7 +18,8 @@ measurement:
   large  -- 6 cm, 4096 cells, 100 Pa, 400 V, dt = T_rf/8000,
             2^25 macro-particles, charge-neutral split 40 % e, 10 % O-, 50 % O2+
 All use 13.56 MHz, a uniform initial load with Maxwellian velocities
-(electrons 3 eV, ions 0.026 eV), C = 1/6 for associative detachment.
+(electrons 3 eV, ions 0.026 eV), C = 1/6 for associative detachment, and
+intra-species Coulomb collisions (ln Lambda = 10) at every cell sort.
 """
 from __future__ import annotations
 
@@ -74,16 +75,17 @@ class Workload:
 
 WORKLOADS = {
     "small": Workload("small", 0.04, 128, 10.0, 100.0, 13.56e6, 1000, 1,
-                      (10_000, 2_000, 10_000), sort_every=10, seed=705049501),
+                      (10_000, 2_000, 10_000), sort_every=10, coulomb_every=10, seed=705049501),
     "prod": Workload("prod", 0.04, 1024, 50.0, 200.0, 13.56e6, 4000, 10,
-                     (2_000_000, 500_000, 2_000_000), sort_every=100, seed=705049502),
+                     (2_000_000, 500_000, 2_000_000), sort_every=100, coulomb_every=100, seed=705049502),
     # 2^25 particles split so that the load is charge neutral (O2+ = e + O-):
     # 40 % e, 10 % O-, 50 % O2+.  Assigning the 50 % to electrons instead leaves
     # 20 % of the negative charge uncompensated (~3 kV of space-charge potential
     # at t = 0), which at 100 Pa starts an ionisation avalanche that multiplies
     # the electron count about tenfold within the first rf cycle.
     "large": Workload("large", 0.06, 4096, 100.0, 400.0, 13.56e6, 8000, 1,
-                      (13_421_773, 3_355_443, 16_777_216), sort_every=10, seed=705049503),
+                      (13_421_773, 3_355_443, 16_777_216), sort_every=10, coulomb_every=10,
+                      seed=705049503),
 }
 
 

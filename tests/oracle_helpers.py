@@ -17,8 +17,9 @@ MASS = (ME, 15.999 * AMU + ME, MO2 - ME)
 
 
 def quiet(wl: Workload, **kw) -> Workload:
-    """A workload with (almost) no self field: tiny weight and no drive."""
-    base = dict(weight=1e-30, voltage_V=0.0)
+    """A workload with (almost) no self field and no Coulomb collisions:
+    tiny weight, no drive."""
+    base = dict(weight=1e-30, voltage_V=0.0, coulomb_every=0)
     base.update(kw)
     return dataclasses.replace(wl.resolved(), **base)
 

@@ -97,7 +97,7 @@ def test_steps_match_oracle(prec, boost):
 
 
 def test_subcycled_ions_match_oracle():
-    wl = ragged_small(ion_subcycle=3, sort_every=6)
+    wl = ragged_small(ion_subcycle=3, sort_every=6, coulomb_every=6)
     sig, thr, loss = build_tables(partner_boost=3e6)
     g = _gpu()(wl, sig, thr, loss, precision="fp32")
     o = O.Oracle(wl, sig, thr, loss, precision="fp32")
@@ -173,3 +173,62 @@ def test_large_size_matches_oracle_sampled():
     g.step(1)
     o.step(1)
     compare(g, o, "fp32", "large step 1", sample_mod=997)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("lnl", [10.0, 1e4])
+def test_coulomb_matches_oracle(prec, lnl):
+    """Intra-species Coulomb collisions with every sort (every 5 steps):
+    ln Lambda = 10 gives small angles only, 1e4 also large angles and the
+    isotropic branch; ragged counts give triangles in odd cells."""
+    wl = ragged_small(sort_every=5, coulomb_every=5, coulomb_log=lnl)
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    done = 0
+    for target in (5, 10, 25, 60):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, prec, f"coulomb step {done}")
+
+
+def test_coulomb_dense_cells_match_oracle():
+    """Thousands of particles of a species per cell: many pairing buckets and
+    several positions per thread."""
+    wl = dataclasses.replace(workload("small"), n_cells=16, n_init=(40001, 20001, 39999), sort_every=2,
+                             coulomb_every=2)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    for k in range(3):
+        g.step(2)
+        o.step(2)
+        compare(g, o, "fp32", f"dense coulomb step {2 * (k + 1)}")
+
+
+def test_coulomb_cell_overflow_is_reported():
+    """More than 16384 particles of one species in a cell: the Coulomb pass
+    reports PIC_EOVERFLOW instead of pairing a part of the cell."""
+    from paper_0705_0495_amd.binding import PicError
+    wl = dataclasses.replace(workload("small"), n_cells=4, n_init=(80000, 0, 80000), sort_every=1,
+                             coulomb_every=1)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    with pytest.raises(PicError) as e:
+        g.sync()
+    assert e.value.code == -5
+
+
+def test_large_size_coulomb_matches_oracle():
+    """The 2^25-particle discharge with the cell sort and the Coulomb pass in
+    its first step; every particle compared (a few thousand particles per
+    species and cell, so equal pairing hashes occur and are ordered by id)."""
+    wl = dataclasses.replace(workload("large"), sort_every=1, coulomb_every=1)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    o.step(1)
+    compare(g, o, "fp32", "large coulomb step 1")

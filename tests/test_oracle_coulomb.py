@@ -112,9 +112,7 @@ def test_triangle_uses_half_the_variance():
 
 def test_tan_half_angle_is_gaussian():
     # ions with a variance of a few 1e-3: the small-angle branch throughout
-    wl = small(n_init=(0, 40000, 0), T_init_eV=(3.0, 0.026, 0.026), sort_every=1, coulomb_every=1,
-               coulomb_log=10.0)
-    wl = quiet(wl, coulomb_log=1e30)
+    wl = quiet(small(n_init=(0, 40000, 0), sort_every=1), coulomb_every=1, coulomb_log=1e30)
     o = Oracle(wl, *zero_tables(), precision="fp64")
     o.log_enable(1 << 17)
     o.step(1)
@@ -147,7 +145,7 @@ def _relaxation_rate_ratio(precision, nu_dt, steps, n_part=200_000, A0=0.4):
     """Relax a bi-Maxwellian O- population (T_x = T/(1+A0), T_y = T_z = T) by
     Coulomb collisions alone and return ln(measured decay of T_perp - T_par)
     over ln(the decay the NRL rate equations give for the same time)."""
-    wl = quiet(small(n_init=(0, n_part, 0), sort_every=1, coulomb_every=1))
+    wl = quiet(small(n_init=(0, n_part, 0), sort_every=1), coulomb_every=1)
     dt = 1.0 / (wl.frequency_Hz * wl.steps_per_period)
     T0 = wl.T_init_eV[1] * QE
     n = wl.weight * n_part / (wl.area_m2 * wl.gap_m)
