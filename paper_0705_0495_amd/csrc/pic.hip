@@ -139,8 +139,7 @@ struct Impl : Base {
     if ((rc = alloc(&s.cell, cap + 4))) return rc;
     if ((rc = alloc(&s.off, cap + 4))) return rc;
     if ((rc = alloc(&s.vx, cap + 4))) return rc;
-    if ((rc = alloc(&s.vy, cap + 4))) return rc;
-    if ((rc = alloc(&s.vz, cap + 4))) return rc;
+    if ((rc = alloc(&s.vyz, 2 * (cap + 4)))) return rc;
     if ((rc = alloc(&s.id, cap + 4))) return rc;
     return 0;
   }
@@ -423,15 +422,14 @@ struct Impl : Base {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int64_t n = Nh[sp];
     std::vector<int32_t> hc(n);
-    std::vector<R> ho(n), hx(n), hy(n), hz(n);
+    std::vector<R> ho(n), hx(n), hyz(2 * n);
     std::vector<uint64_t> hi(n);
     const Store<R>& s = D.st[sp];
     if (n > 0) {
       HIPCHK(c, hipMemcpyAsync(hc.data(), s.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipMemcpyAsync(ho.data(), s.off, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipMemcpyAsync(hx.data(), s.vx, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipMemcpyAsync(hy.data(), s.vy, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipMemcpyAsync(hz.data(), s.vz, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hyz.data(), s.vyz, 2 * n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipMemcpyAsync(hi.data(), s.id, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -444,8 +442,8 @@ struct Impl : Base {
         if (off) off[k] = (double)ho[i];
         if (v) {
           v[3 * k] = (double)hx[i];
-          v[3 * k + 1] = (double)hy[i];
-          v[3 * k + 2] = (double)hz[i];
+          v[3 * k + 1] = (double)hyz[2 * i];
+          v[3 * k + 2] = (double)hyz[2 * i + 1];
         }
       }
       k++;

@@ -69,6 +69,14 @@ struct Birth {
   R off, v0, v1, v2;
 };
 
+// a candidate of the null-collision test in the state the push leaves it in
+template <class R>
+struct Cand {
+  int32_t slot, cell;
+  R off, vx;
+  uint64_t id;
+};
+
 template <class R>
 struct Request {
   int32_t sp, chan, slot, cell;
@@ -82,10 +90,27 @@ struct Store {
   int32_t* cell;
   R* off;
   R* vx;
-  R* vy;
-  R* vz;
+  R* vyz;  // (vy, vz) interleaved: one 8- or 16-byte access per particle
   uint64_t* id;
 };
+
+template <class R> struct Pair2;
+template <> struct Pair2<float> { using T = float2; };
+template <> struct Pair2<double> { using T = double2; };
+
+template <class R>
+__device__ __forceinline__ void ld_yz(const Store<R>& s, int64_t i, R& y, R& z) {
+  const typename Pair2<R>::T p = *(const typename Pair2<R>::T*)(s.vyz + 2 * i);
+  y = p.x;
+  z = p.y;
+}
+template <class R>
+__device__ __forceinline__ void st_yz(const Store<R>& s, int64_t i, R y, R z) {
+  typename Pair2<R>::T p;
+  p.x = y;
+  p.y = z;
+  *(typename Pair2<R>::T*)(s.vyz + 2 * i) = p;
+}
 
 template <class R>
 struct Dev {
@@ -110,8 +135,8 @@ struct Dev {
   int32_t* bhist;   // [NBUCKET] births per creator-id bucket
   int32_t* boff;    // [NBUCKET+1]
   int32_t* perm;    // [nb_cap] births grouped by bucket
-  int32_t* cand[3]; // candidates of the null-collision test: tile t of species s
-                    // writes its slots to cand[s][t*TILE ...]
+  Cand<R>* cand[3]; // candidates of the null-collision test: tile t of species s
+                    // writes them to cand[s][t*TILE ...]
   int32_t* tcnt[3]; // candidates per tile
   int32_t* ncand;   // [3] (unused)
   Request<R>* req;
@@ -601,13 +626,17 @@ __device__ __forceinline__ bool gas_event(const Consts<R>& C, const Dev<R>& D, i
 }
 
 template <class R, int S>
-__device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int slot, uint32_t n) {
+__device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int64_t r, uint32_t n) {
   const Store<R> st = D.st[S];
   const int N = C.N;
-  const int cell = st.cell[slot];
-  const R off = st.off[slot];
-  R v[3] = {st.vx[slot], st.vy[slot], st.vz[slot]};
-  const uint64_t id = st.id[slot];
+  const Cand<R> k = D.cand[S][r];
+  const int slot = k.slot;
+  const int cell = k.cell;
+  const R off = k.off;
+  R v[3];
+  v[0] = k.vx;
+  ld_yz(st, slot, v[1], v[2]);
+  const uint64_t id = k.id;
   const uint4 w = rng(C, id, n, 0);
   const double U = unif52(w.x, w.y);
   double cum = 0.0;
@@ -669,8 +698,7 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
     atomicAdd(&G.ev[hit], 1);
     if (gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n)) {
       st.vx[slot] = v[0];
-      st.vy[slot] = v[1];
-      st.vz[slot] = v[2];
+      st_yz(st, slot, v[1], v[2]);
     } else {
       st.cell[slot] = DEAD;
       deposit_global(D, N, S, cell, off, -1);
@@ -700,8 +728,7 @@ __device__ __forceinline__ void collide_group(const Consts<R>& C, const Dev<R>& 
   for (int e = tid; e < tot; e += COLL_TPB) {
     int k = 0;
     while (e >= pre[k + 1]) k++;
-    const int slot = D.cand[S][(tile0 + k) * TILE + (e - pre[k])];
-    collide_one<R, S>(C, D, G, slot, n);
+    collide_one<R, S>(C, D, G, (tile0 + k) * TILE + (e - pre[k]), n);
   }
   __syncthreads();
 }
@@ -762,16 +789,16 @@ template <> struct Vec4<double> {
   }
 };
 
+// add a packed (count << 40 | sum of 24-bit fractions) to one cell
 template <class R>
 __device__ __forceinline__ void deposit_win(PushLds<R>& L, const Dev<R>& D, int N, int sp, int base, int cell,
-                                            R off) {
-  const int32_t f = frac24(off);
+                                            uint64_t packed) {
   const int idx = cell - base;
   if ((unsigned)idx < (unsigned)WIN) {
-    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)((1ull << 40) + (uint64_t)f));
+    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)packed);
   } else {
-    atomicAdd(&D.cnt[(size_t)sp * N + cell], 1);
-    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)f);
+    atomicAdd(&D.cnt[(size_t)sp * N + cell], (int)(packed >> 40));
+    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)(packed & F_MASK));
   }
 }
 
@@ -819,6 +846,9 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   }
   const bool was_dead[4] = {c[0] == DEAD, c[1] == DEAD, c[2] == DEAD, c[3] == DEAD};
   int candmask = 0;
+  // a thread's consecutive particles mostly share a cell: one atomic per run
+  int run_cell = -1;
+  uint64_t run_val = 0;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     if (was_dead[q]) continue;
@@ -855,16 +885,26 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       continue;
     }
     c[q] = cn;
-    deposit_win(L, D, N, S, base, cn, o);
+    if (cn != run_cell) {
+      if (run_cell >= 0) deposit_win(L, D, N, S, base, run_cell, run_val);
+      run_cell = cn;
+      run_val = 0;
+    }
+    run_val += (1ull << 40) + (uint64_t)frac24(o);
     const uint4 w = rng(C, id[q], n, 0);
     if ((uint64_t)w.x < T0 && unif52(w.x, w.y) < pmax) {
       candmask |= 1 << q;
     } else if (S == 0) {
-      if (cn == C.cmid) diag_alive<R, S>(C, L.G, cn, vx[q], st.vy[s0 + q], st.vz[s0 + q]);
+      if (cn == C.cmid) {
+        R vy, vz;
+        ld_yz(st, s0 + q, vy, vz);
+        diag_alive<R, S>(C, L.G, cn, vx[q], vy, vz);
+      }
     } else if (S == 1) {
       diag_alive<R, S>(C, L.G, cn, vx[q], (R)0, (R)0);
     }
   }
+  if (run_cell >= 0) deposit_win(L, D, N, S, base, run_cell, run_val);
   if (full) {
     *(int4*)(st.cell + s0) = make_int4(c[0], c[1], c[2], c[3]);
     Vec4<R>::store(st.off + s0, off);
@@ -893,10 +933,17 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   if (lane == 63 && wtot > 0) wbase = atomicAdd(&L.ncand, wtot);
   wbase = __shfl(wbase, 63);
   int pos = wbase + incl - mine;
-  int32_t* region = D.cand[S] + t0;
 #pragma unroll
   for (int q = 0; q < 4; q++)
-    if (candmask & (1 << q)) region[pos++] = (int32_t)(s0 + q);
+    if (candmask & (1 << q)) {
+      Cand<R> k;
+      k.slot = (int32_t)(s0 + q);
+      k.cell = c[q];
+      k.off = off[q];
+      k.vx = vx[q];
+      k.id = id[q];
+      D.cand[S][t0 + pos++] = k;
+    }
   __syncthreads();
   if (tid == 0) D.tcnt[S][t0 / TILE] = L.ncand;
   int32_t* cnt_s = D.cnt + (size_t)S * N;
@@ -1045,7 +1092,10 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
       if (p >= 0 && D.st[t].cell[p] != DEAD) {
         const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
         const Store<R> ts = D.st[q.sp], ps = D.st[t];
-        const R gx = ts.vx[q.slot] - ps.vx[p], gy = ts.vy[q.slot] - ps.vy[p], gz = ts.vz[q.slot] - ps.vz[p];
+        R ty, tz, py, pz;
+        ld_yz(ts, q.slot, ty, tz);
+        ld_yz(ps, p, py, pz);
+        const R gx = ts.vx[q.slot] - ps.vx[p], gy = ty - py, gz = tz - pz;
         const R g2 = (gx * gx + gy * gy) + gz * gz;
         const R g = Sqrt(g2);
         const R Erel = C.hmu_c[pi] * g2;
@@ -1086,8 +1136,11 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
     // (19): inelastic e-O- collision, O- split into O + e, e-e elastic
     const Store<R> es = D.st[0], ns = D.st[1];
     const int p = L.rpart[r];
-    const R T[3] = {es.vx[q.slot], es.vy[q.slot], es.vz[q.slot]};
-    const R P[3] = {ns.vx[p], ns.vy[p], ns.vz[p]};
+    R T[3], P[3];
+    T[0] = es.vx[q.slot];
+    ld_yz(es, q.slot, T[1], T[2]);
+    P[0] = ns.vx[p];
+    ld_yz(ns, p, P[1], P[2]);
     const R a = C.a_c[1], b = C.b_c[1];
     const R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
     const R g2 = (gx * gx + gy * gy) + gz * gz;
@@ -1108,8 +1161,7 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
     }
     ee_elastic<R>(ve, vn, n2);
     es.vx[q.slot] = ve[0];
-    es.vy[q.slot] = ve[1];
-    es.vz[q.slot] = ve[2];
+    st_yz(es, q.slot, ve[1], ve[2]);
     const int pc = ns.cell[p];
     const R po = ns.off[p];
     kill_particle(C, D, 1, p);
@@ -1220,8 +1272,7 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
         st.cell[slot] = rec.cell;
         st.off[slot] = rec.off;
         st.vx[slot] = rec.v0;
-        st.vy[slot] = rec.v1;
-        st.vz[slot] = rec.v2;
+        st_yz(st, slot, rec.v1, rec.v2);
         st.id[slot] = next + (uint64_t)rank;
       }
     }
@@ -1412,8 +1463,9 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       cell[j] = in ? a.cell[slot] : DEAD;
       off[j] = in ? a.off[slot] : (R)0;
       vx[j] = in ? a.vx[slot] : (R)0;
-      vy[j] = in ? a.vy[slot] : (R)0;
-      vz[j] = in ? a.vz[slot] : (R)0;
+      vy[j] = (R)0;
+      vz[j] = (R)0;
+      if (in) ld_yz(a, slot, vy[j], vz[j]);
       id[j] = in ? a.id[slot] : 0;
     }
     __syncthreads();
@@ -1456,8 +1508,7 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       b.cell[dst] = cell[j];
       b.off[dst] = off[j];
       b.vx[dst] = vx[j];
-      b.vy[dst] = vy[j];
-      b.vz[dst] = vz[j];
+      st_yz(b, dst, vy[j], vz[j]);
       b.id[dst] = id[j];
     }
     __syncthreads();
@@ -1628,15 +1679,22 @@ __global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uin
           continue;
         }
         const int i0 = a + L.ord[0], i1 = a + L.ord[1], i2 = a + L.ord[2];
-        R v0[3] = {S.vx[i0], S.vy[i0], S.vz[i0]};
-        R v1[3] = {S.vx[i1], S.vy[i1], S.vz[i1]};
-        R v2[3] = {S.vx[i2], S.vy[i2], S.vz[i2]};
+        R v0[3], v1[3], v2[3];
+        v0[0] = S.vx[i0];
+        ld_yz(S, i0, v0[1], v0[2]);
+        v1[0] = S.vx[i1];
+        ld_yz(S, i1, v1[1], v1[2]);
+        v2[0] = S.vx[i2];
+        ld_yz(S, i2, v2[1], v2[2]);
         ta_pair<R>(C, v0, v1, ch, S.id[i0], n, 17);
         ta_pair<R>(C, v1, v2, ch, S.id[i1], n, 18);
         ta_pair<R>(C, v2, v0, ch, S.id[i2], n, 19);
-        S.vx[i0] = v0[0]; S.vy[i0] = v0[1]; S.vz[i0] = v0[2];
-        S.vx[i1] = v1[0]; S.vy[i1] = v1[1]; S.vz[i1] = v1[2];
-        S.vx[i2] = v2[0]; S.vy[i2] = v2[1]; S.vz[i2] = v2[2];
+        S.vx[i0] = v0[0];
+        st_yz(S, i0, v0[1], v0[2]);
+        S.vx[i1] = v1[0];
+        st_yz(S, i1, v1[1], v1[2]);
+        S.vx[i2] = v2[0];
+        st_yz(S, i2, v2[1], v2[2]);
         continue;
       }
       const int q = first + 2 * p;
@@ -1645,11 +1703,16 @@ __global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uin
         continue;
       }
       const int ia = a + L.ord[q], ib = a + L.ord[q + 1];
-      R va[3] = {S.vx[ia], S.vy[ia], S.vz[ia]};
-      R vb[3] = {S.vx[ib], S.vy[ib], S.vz[ib]};
+      R va[3], vb[3];
+      va[0] = S.vx[ia];
+      ld_yz(S, ia, va[1], va[2]);
+      vb[0] = S.vx[ib];
+      ld_yz(S, ib, vb[1], vb[2]);
       ta_pair<R>(C, va, vb, cf, S.id[ia], n, 17);
-      S.vx[ia] = va[0]; S.vy[ia] = va[1]; S.vz[ia] = va[2];
-      S.vx[ib] = vb[0]; S.vy[ib] = vb[1]; S.vz[ib] = vb[2];
+      S.vx[ia] = va[0];
+      st_yz(S, ia, va[1], va[2]);
+      S.vx[ib] = vb[0];
+      st_yz(S, ib, vb[1], vb[2]);
     }
     __syncthreads();
   }
@@ -1682,8 +1745,7 @@ __global__ void k_load(Consts<R> C, Dev<R> D, int64_t n_e, int64_t n_n, int64_t 
   R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
   R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
   st.vx[i] = C.vth0[s] * (r1 * cos2pi<R>(a1));
-  st.vy[i] = C.vth0[s] * (r1 * sin2pi<R>(a1));
-  st.vz[i] = C.vth0[s] * (r2 * cos2pi<R>(a2));
+  st_yz(st, i, C.vth0[s] * (r1 * sin2pi<R>(a1)), C.vth0[s] * (r2 * cos2pi<R>(a2)));
 }
 
 template <class R>
