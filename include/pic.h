@@ -67,11 +67,11 @@ typedef struct {
   int32_t ion_subcycle;       /* ions are moved every ion_subcycle steps with tau = ion_subcycle * dt */
   int32_t sort_every;         /* particles are re-sorted into cells every sort_every steps */
   int32_t drive_dc;           /* 0: sinusoidal drive; 1: constant U = voltage (test switch) */
-  int64_t n_init[3];          /* initial macro particles per species */
+  int64_t n_init[3];          /* initial macro particles per species, at most 2^30 - 65536 */
   double T_init_eV[3];        /* initial Maxwellian temperatures */
   uint64_t seed;              /* Philox key */
   int32_t precision;          /* PIC_FP32 or PIC_FP64 particle state */
-  int64_t capacity[3];        /* store capacity per species; 0 -> 2 n_init + 65536 */
+  int64_t capacity[3];        /* store capacity per species (< 2^30); 0 -> 2 n_init + 65536 */
   int32_t eedf_bins;          /* electron energy histogram at x = L/2, 0 <= bins <= 256 */
   double eedf_emax_eV;
   int32_t fneg_xbins;         /* O- f(E,x), E = sign(v_x) M v_x^2 / 2; xbins*ebins <= 2048 */

@@ -242,8 +242,8 @@ struct Impl : Base {
     for (int s = 0; s < 3; s++) {
       int64_t cap = G.capacity[s] > 0 ? G.capacity[s] : 2 * G.n_init[s] + 65536;
       cap = (cap + 3) & ~(int64_t)3;
-      if (cap < G.n_init[s] || cap >= ((int64_t)1 << 31) - 8)
-        return fail(c, PIC_EINVAL, "capacity must hold the initial load and stay below 2^31");
+      if (cap < G.n_init[s] || cap >= ((int64_t)1 << 30) - 8)
+        return fail(c, PIC_EINVAL, "capacity must hold the initial load and stay below 2^30");
       D.cap[s] = cap;
       if ((rc = alloc_store(D.st[s], cap))) return rc;
       if ((rc = alloc_store(D.alt[s], cap))) return rc;
@@ -534,7 +534,7 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       (g->coulomb_every > 0 && (g->coulomb_every % g->sort_every != 0 || !(gas->coulomb_log > 0))))
     return PIC_EINVAL;
   for (int s = 0; s < 3; s++)
-    if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 31) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;
+    if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 30) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;
   if (g->n_init[0] + g->n_init[1] + g->n_init[2] > (int64_t)(ID_MASK)) return PIC_EINVAL;
   pic_ctx* c = new pic_ctx();
   c->G = *g;

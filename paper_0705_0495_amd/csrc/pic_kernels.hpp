@@ -1409,23 +1409,36 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
 }
 
 constexpr int SORT_TPB = 256;
-constexpr int SORT_PER = 8;
+constexpr int SORT_PER = 4;
 constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
-constexpr int SORT_WIN = 1024;
+constexpr int SORT_WIN = 512;  // cells around the middle of a chunk
 
-// Each workgroup moves one contiguous chunk of a store.  All fields of the
-// chunk are loaded before the ranking.  Inside a wave the lanes of equal cell
-// get consecutive destinations; one LDS atomic per (wave, cell) orders the
-// waves, one global atomic per (chunk, cell) reserves the destination range,
-// so loads and stores are coalesced.
+template <class R>
+struct SortLds {
+  int32_t cnt[SORT_WIN];   // particles of the chunk per window cell
+  int32_t lst[SORT_WIN];   // their first position in the staged chunk
+  int32_t gb[SORT_WIN];    // their first destination in the sorted store
+  int32_t wsum[SORT_TPB / 64];
+  int32_t wbase, nst;
+  int32_t cell[SORT_CHUNK];
+  R off[SORT_CHUNK];
+  R vx[SORT_CHUNK];
+  typename Pair2<R>::T vyz[SORT_CHUNK];
+  uint64_t id[SORT_CHUNK];
+};
+
+// Each workgroup sorts one contiguous chunk of a store in LDS and writes it
+// out in cell runs, so that consecutive threads write consecutive addresses of
+// the destination.  Ranks inside a wave come from ballots (one LDS atomic per
+// wave and cell); one global atomic per (chunk, cell) reserves the run.  The
+// order inside a cell is arbitrary: no result depends on it.  Particles whose
+// cell lies outside the chunk's window take a global atomic of their own.
 template <class R>
 __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D) {
-  __shared__ int32_t lcnt[SORT_WIN];
-  __shared__ int32_t lbase[SORT_WIN];
-  __shared__ int32_t wbase;
+  __shared__ SortLds<R> L;
   const int N = C.N;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int lane = tid & 63, wv = tid >> 6;
   const uint64_t below = (1ull << lane) - 1;
   int64_t Ns[3], nch[3];
   for (int s = 0; s < 3; s++) {
@@ -1449,10 +1462,12 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
     int32_t* cur = D.cursor + (size_t)s * N;
     const int32_t* seg = D.seg + (size_t)s * (N + 1);
     if (tid == 0) {
-      const int32_t cf = a.cell[c0];
-      wbase = (cf == DEAD ? 0 : cf) - 64;
+      int32_t cm = a.cell[min(c0 + SORT_CHUNK / 2, Ns[s] - 1)];
+      if (cm == DEAD) cm = a.cell[c0];
+      if (cm == DEAD) cm = 0;
+      L.wbase = cm - SORT_WIN / 2;
     }
-    for (int i = tid; i < SORT_WIN; i += SORT_TPB) lcnt[i] = 0;
+    for (int i = tid; i < SORT_WIN; i += SORT_TPB) L.cnt[i] = 0;
     int32_t cell[SORT_PER], rank[SORT_PER];
     R off[SORT_PER], vx[SORT_PER], vy[SORT_PER], vz[SORT_PER];
     uint64_t id[SORT_PER];
@@ -1469,7 +1484,7 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       id[j] = in ? a.id[slot] : 0;
     }
     __syncthreads();
-    const int base = wbase;
+    const int base = L.wbase;
 #pragma unroll
     for (int j = 0; j < SORT_PER; j++) {
       const bool alive = cell[j] != DEAD;
@@ -1484,8 +1499,9 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
         int gb = 0;
         if (lane == leader) {
           const int idx = lkey - base;
-          // window cells: LDS offset (made global below); others: global offset now
-          gb = ((unsigned)idx < (unsigned)SORT_WIN) ? atomicAdd(&lcnt[idx], cnt) : (atomicAdd(&cur[lkey], cnt) | (1 << 30));
+          // window cells: rank in the chunk; others: their destination now
+          gb = ((unsigned)idx < (unsigned)SORT_WIN) ? atomicAdd(&L.cnt[idx], cnt)
+                                                     : (atomicAdd(&cur[lkey], cnt) | (1 << 30));
         }
         gb = __shfl(gb, leader);
         if (key == lkey) rank[j] = gb + __popcll(peers & below);
@@ -1493,23 +1509,75 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       }
     }
     __syncthreads();
-    for (int i = tid; i < SORT_WIN; i += SORT_TPB)
-      if (lcnt[i] > 0) lbase[i] = atomicAdd(&cur[base + i], lcnt[i]);
+    // global runs and the exclusive scan of the window counts
+    int32_t loc[SORT_WIN / SORT_TPB];
+    int32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < SORT_WIN / SORT_TPB; q++) {
+      const int i = tid * (SORT_WIN / SORT_TPB) + q;
+      loc[q] = L.cnt[i];
+      if (loc[q] > 0) L.gb[i] = atomicAdd(&cur[base + i], loc[q]);
+      sum += loc[q];
+    }
+    int32_t x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) L.wsum[wv] = x;
+    __syncthreads();
+    int32_t run = x - sum;
+    for (int w = 0; w < wv; w++) run += L.wsum[w];
+#pragma unroll
+    for (int q = 0; q < SORT_WIN / SORT_TPB; q++) {
+      L.lst[tid * (SORT_WIN / SORT_TPB) + q] = run;
+      run += loc[q];
+    }
+    if (tid == SORT_TPB - 1) L.nst = run;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < SORT_PER; j++) {
       if (cell[j] == DEAD) continue;
       const int idx = cell[j] - base;
-      const int32_t dst = ((unsigned)idx < (unsigned)SORT_WIN) ? lbase[idx] + rank[j] : (rank[j] & ~(1 << 30));
-      if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1]) {
+      if ((unsigned)idx < (unsigned)SORT_WIN) {
+        const int p = L.lst[idx] + rank[j];
+        L.cell[p] = cell[j];
+        L.off[p] = off[j];
+        L.vx[p] = vx[j];
+        typename Pair2<R>::T yz;
+        yz.x = vy[j];
+        yz.y = vz[j];
+        L.vyz[p] = yz;
+        L.id[p] = id[j];
+      } else {
+        const int32_t dst = rank[j] & ~(1 << 30);
+        if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1]) {
+          atomicOr(&D.ctr->err, ERR_SORT);
+          continue;
+        }
+        b.cell[dst] = cell[j];
+        b.off[dst] = off[j];
+        b.vx[dst] = vx[j];
+        st_yz(b, dst, vy[j], vz[j]);
+        b.id[dst] = id[j];
+      }
+    }
+    __syncthreads();
+    const int nst = L.nst;
+    for (int k = tid; k < nst; k += SORT_TPB) {
+      const int32_t cl = L.cell[k];
+      const int idx = cl - base;
+      const int32_t dst = L.gb[idx] + (k - L.lst[idx]);
+      if (dst < seg[cl] || dst >= seg[cl + 1]) {
         atomicOr(&D.ctr->err, ERR_SORT);
         continue;
       }
-      b.cell[dst] = cell[j];
-      b.off[dst] = off[j];
-      b.vx[dst] = vx[j];
-      st_yz(b, dst, vy[j], vz[j]);
-      b.id[dst] = id[j];
+      b.cell[dst] = cl;
+      b.off[dst] = L.off[k];
+      b.vx[dst] = L.vx[k];
+      *(typename Pair2<R>::T*)(b.vyz + 2 * (int64_t)dst) = L.vyz[k];
+      b.id[dst] = L.id[k];
     }
     __syncthreads();
   }
