@@ -1,0 +1,101 @@
+"""Long runs: cycle-averaged moments of the GPU (FP32 particle state) against
+the CPU oracle in double precision.
+
+The trajectories of two precisions separate after a few rf cycles, so the
+comparison is statistical: three seeds per side, moments averaged over rf
+cycles, and the difference of the three-seed means set against the
+seed-to-seed spread of the oracle runs.  The oracle's moments are stored in
+``tests/golden/<workload>_fp64_moments.npz``, written by
+``tests/golden/moments.py`` (oracle only).
+
+Metrics (for each of n_e, n_O-, n_O2+, phi, the EEDF at L/2 and the events per
+cycle): the L2-relative difference of the three-seed means, and for the
+densities the largest relative difference at nodes above 10 % of the peak.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from pic_inputs import build_tables
+from tests.golden.moments import averages, node_volumes, seeded
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NAMES = ["n_e", "n_O-", "n_O2+"]
+
+
+def gpu_run(name, k, cycles, skip):
+    from paper_0705_0495_amd import Discharge
+    wl = seeded(name, k)
+    g = Discharge(wl, *build_tables(), precision="fp32")
+    M = wl.steps_per_period
+    last = np.zeros(19)
+
+    def cycle():
+        nonlocal last
+        g.step(M)
+        m = g.moments()
+        ev = np.asarray(m["events"], float)
+        d = {"density": np.asarray(m["density"]).reshape(3, -1), "phi": np.asarray(m["phi"]),
+             "eedf": m["eedf"] / max(1, m["eedf"].sum()), "events": ev - last}
+        last = ev
+        return d
+
+    out = averages(cycle, cycles, skip)
+    g.close()
+    return out
+
+
+def l2rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def statement(name):
+    ref = np.load(os.path.join(GOLD, f"{name}_fp64_moments.npz"))
+    cycles, skip = int(ref["cycles"]), int(ref["skip"])
+    runs = [gpu_run(name, k, cycles, skip) for k in range(len(ref["seed_offsets"]))]
+    gpu = {key: np.stack([r[key] for r in runs]) for key in runs[0]}
+    rows = []
+    quantities = [(NAMES[s], gpu["density"][:, s], ref["density"][:, s]) for s in range(3)]
+    quantities += [("phi", gpu["phi"], ref["phi"]), ("EEDF(L/2)", gpu["eedf"], ref["eedf"]),
+                   ("events/cycle", gpu["events"], ref["events"])]
+    for label, G, O in quantities:
+        err = l2rel(G.mean(0), O.mean(0))
+        spread = np.mean([l2rel(O[i], O[j]) for i, j in itertools.combinations(range(len(O)), 2)])
+        # two independent three-seed means differ by about spread / sqrt(3)
+        expect = spread / np.sqrt(len(O))
+        mx = float("nan")
+        if label.startswith("n_"):
+            o = O.mean(0)
+            m = o > 0.1 * o.max()
+            mx = float(np.max(np.abs(G.mean(0)[m] - o[m]) / o[m]))
+        rows.append((label, err, mx, spread, expect))
+    print(f"\n{name}: FP32 GPU vs FP64 oracle, 3 seeds, cycles {skip + 1}-{cycles} averaged")
+    print(f"{'moment':14s} {'L2 rel':>8s} {'max rel':>8s} {'seed spread':>11s} {'expected':>9s}")
+    for label, err, mx, spread, expect in rows:
+        print(f"{label:14s} {err:8.4f} {mx:8.4f} {spread:11.4f} {expect:9.4f}")
+    return rows
+
+
+def test_small_long_run_moments_agree_with_fp64_oracle():
+    """20 rf cycles of the 22k-particle discharge: the difference is
+    consistent with the statistical noise (a few per cent at this size)."""
+    for label, err, mx, spread, expect in statement("small"):
+        assert err <= max(0.02, 3.0 * expect), (label, err, expect)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "prod_fp64_moments.npz")),
+                    reason="oracle moments of the production discharge not generated")
+def test_prod_long_run_moments_agree_with_fp64_oracle_within_2pct():
+    """The 4.5M-particle production discharge, cycles 2-3: densities of e and
+    O2+, the potential, the EEDF and the event rates within 2 %."""
+    for label, err, mx, spread, expect in statement("prod"):
+        if label == "n_O-":
+            assert err <= max(0.02, 3.0 * expect), (label, err, expect)
+        else:
+            assert err <= 0.02, (label, err, expect)
