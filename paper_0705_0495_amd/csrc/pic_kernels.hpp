@@ -357,84 +357,128 @@ constexpr int NMAX_CELLS = 8192;
 constexpr int FIELD_PER_MAX = (NMAX_CELLS + FIELD_TPB) / FIELD_TPB;
 
 // mode 0: solve only (creation); mode 1: step (diagnostics, clear the
-// accumulators of the species moved in this step).  A single workgroup; each
-// thread owns PER consecutive nodes and issues all of its loads before any
-// dependent arithmetic, so the kernel waits for one memory round trip.
+// accumulators of the species moved in this step).  A single workgroup.
+// Global memory is read and written with node i = tid + k * FIELD_TPB
+// (coalesced); the prefix sums run over LDS with each thread owning PER
+// consecutive nodes.
 struct FieldLds {
-  double phis[NMAX_CELLS + 1];
-  __int128 scA[FIELD_TPB];
-  __int128 scB[FIELD_TPB];
+  union {
+    int64_t q[NMAX_CELLS + 1];   // net charge per node, then
+    double phi[NMAX_CELLS + 1];  // the potential (each slot read before it is overwritten)
+  } v;
+  __int128 wsA[FIELD_TPB / 64];
+  __int128 wsB[FIELD_TPB / 64];
+  int64_t q0, qN;
 };
+
+// inclusive prefix sum of a 128-bit integer across the lanes of a wave
+__device__ __forceinline__ __int128 wave_scan_i128(__int128 x) {
+  const int lane = threadIdx.x & 63;
+  uint64_t lo = (uint64_t)x, hi = (uint64_t)((unsigned __int128)x >> 64);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t ylo = __shfl_up(lo, d), yhi = __shfl_up(hi, d);
+    if (lane >= d) {
+      const uint64_t s = lo + ylo;
+      hi = hi + yhi + (s < lo ? 1 : 0);
+      lo = s;
+    }
+  }
+  return (__int128)(((unsigned __int128)hi << 64) | lo);
+}
 
 template <class R, int PER>
 __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64_t n, FieldLds& FL) {
-  double* phis = FL.phis;
-  __int128* scA = FL.scA;
-  __int128* scB = FL.scB;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int N = C.N;
   const double U = D.U[n % C.M];
   const bool ion = (n % C.nsub) == 0;
-  const int i0 = min(tid * PER, N + 1);
-  const int i1 = min(i0 + PER, N + 1);
+  // 1. node charge Q_s[i] = 2^24 cnt[i] - F[i] + F[i-1] (coalesced)
   int32_t cn[3][PER];
-  int64_t Fc[3][PER];
-  int64_t Fp[3];
+  int64_t Fc[3][PER], Fm[3][PER];
   double pa[PER];
 #pragma unroll
-  for (int s = 0; s < 3; s++) {
-    Fp[s] = (i0 >= 1 && i0 < i1) ? D.F[s * N + i0 - 1] : 0;
+  for (int s = 0; s < 3; s++)
 #pragma unroll
     for (int k = 0; k < PER; k++) {
-      const int i = i0 + k;
-      const bool in = i < i1 && i < N;
-      cn[s][k] = in ? D.cnt[s * N + i] : 0;
-      Fc[s][k] = in ? D.F[s * N + i] : 0;
+      const int i = tid + k * FIELD_TPB;
+      cn[s][k] = i < N ? D.cnt[s * N + i] : 0;
+      Fc[s][k] = i < N ? D.F[s * N + i] : 0;
+      Fm[s][k] = (i >= 1 && i <= N) ? D.F[s * N + i - 1] : 0;
     }
-  }
-#pragma unroll
-  for (int k = 0; k < PER; k++) pa[k] = (i0 + k < i1 && mode == 1) ? D.phiacc[i0 + k] : 0.0;
-  int64_t qloc[PER];
-  __int128 a = 0, b = 0;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const int i = i0 + k;
-    qloc[k] = 0;
-    if (i >= i1) continue;
+    const int i = tid + k * FIELD_TPB;
+    pa[k] = (i <= N && mode == 1) ? D.phiacc[i] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = tid + k * FIELD_TPB;
+    if (i > N) continue;
     int64_t Qs[3];
 #pragma unroll
     for (int s = 0; s < 3; s++) {
-      int64_t v = ((int64_t)cn[s][k] << 24) - Fc[s][k];
-      v += (k == 0) ? Fp[s] : Fc[s][k - 1];
+      const int64_t v = (((int64_t)cn[s][k] << 24) - Fc[s][k]) + Fm[s][k];
       Qs[s] = v;
       D.Qcur[s * (N + 1) + i] = v;
       // one addition per node and step: the order of the sums is fixed
       if (mode == 1) atomicAdd((unsigned long long*)&D.Qacc[s * (N + 1) + i], (unsigned long long)v);
     }
     const int64_t q = (Qs[2] - Qs[0]) - Qs[1];
-    qloc[k] = q;
-    if (i >= 1 && i <= N - 1) {
-      a += (__int128)i * q;
-      b += (__int128)(N - i) * q;
+    FL.v.q[i] = q;
+    if (i == 0) FL.q0 = q;
+    if (i == N) FL.qN = q;
+  }
+  if (mode == 1) {
+    // the passes of this step deposit every moved particle afresh
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+      if (s != 0 && !ion) continue;
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int i = tid + k * FIELD_TPB;
+        if (i < N) {
+          D.cnt[s * N + i] = 0;
+          D.F[s * N + i] = 0;
+        }
+      }
     }
   }
-  scA[tid] = a;
-  scB[tid] = b;
   __syncthreads();
-  for (int d = 1; d < FIELD_TPB; d <<= 1) {
-    __int128 xa = 0, xb = 0;
-    if (tid >= d) {
-      xa = scA[tid - d];
-      xb = scB[tid - d];
+  // 2. potential from the exact discrete Green's function, contiguous nodes
+  const int i0 = min(tid * PER, N + 1);
+  const int i1 = min(i0 + PER, N + 1);
+  int64_t qloc[PER];
+  __int128 a = 0, b = 0;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = i0 + k;
+    qloc[k] = i < i1 ? FL.v.q[i] : 0;
+    if (i >= 1 && i <= N - 1 && i < i1) {
+      a += (__int128)i * qloc[k];
+      b += (__int128)(N - i) * qloc[k];
     }
-    __syncthreads();
-    scA[tid] += xa;
-    scB[tid] += xb;
-    __syncthreads();
   }
-  __int128 S1 = scA[tid] - a;   // sum_{j < i0} j q_j
-  __int128 PB = scB[tid] - b;   // sum_{j < i0} (N-j) q_j
-  const __int128 TB = scB[FIELD_TPB - 1];
+  // block-wide exclusive prefix sums of a and b: waves by shuffles, then the
+  // 16 wave totals (integer sums: exact in any order)
+  const __int128 ia = wave_scan_i128(a), ib = wave_scan_i128(b);
+  if (lane == 63) {
+    FL.wsA[wv] = ia;
+    FL.wsB[wv] = ib;
+  }
+  __syncthreads();
+  __int128 S1 = ia - a;   // sum_{j < i0} j q_j
+  __int128 PB = ib - b;   // sum_{j < i0} (N-j) q_j
+  __int128 TB = 0;
+#pragma unroll
+  for (int w = 0; w < FIELD_TPB / 64; w++) {
+    if (w < wv) {
+      S1 += FL.wsA[w];
+      PB += FL.wsB[w];
+    }
+    TB += FL.wsB[w];
+  }
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int i = i0 + k;
@@ -454,31 +498,18 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
       const double y = C.cphi * i128_to_double(T);
       ph = (x + y) / (double)N;
     }
-    phis[i] = ph;
-  }
-  if (mode == 1) {
-    // the passes of this step deposit every moved particle afresh
-#pragma unroll
-    for (int s = 0; s < 3; s++) {
-      if (s != 0 && !ion) continue;
-#pragma unroll
-      for (int k = 0; k < PER; k++) {
-        const int i = i0 + k;
-        if (i < i1 && i < N) {
-          D.cnt[s * N + i] = 0;
-          D.F[s * N + i] = 0;
-        }
-      }
-    }
+    FL.v.phi[i] = ph;
   }
   __syncthreads();
+  // 3. field, with the half-cell Gauss law at the electrodes (coalesced)
+  const double* phis = FL.v.phi;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const int i = i0 + k;
-    if (i >= i1) continue;
+    const int i = tid + k * FIELD_TPB;
+    if (i > N) continue;
     double e;
-    if (i == 0) e = (phis[0] - phis[1]) * C.invdx - C.cE * (double)qloc[k];
-    else if (i == N) e = (phis[N - 1] - phis[N]) * C.invdx + C.cE * (double)qloc[k];
+    if (i == 0) e = (phis[0] - phis[1]) * C.invdx - C.cE * (double)FL.q0;
+    else if (i == N) e = (phis[N - 1] - phis[N]) * C.invdx + C.cE * (double)FL.qN;
     else e = (phis[i - 1] - phis[i + 1]) * C.inv2dx;
     D.E[i] = e;
     D.phi[i] = phis[i];
@@ -1059,35 +1090,36 @@ struct ClaimLds {
 };
 
 template <class R>
-__device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, uint64_t* bk, int32_t* bi, int nr,
-                               uint32_t n) {
+__device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, int nr, uint32_t n) {
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int N = C.N;
-  for (int r = 0; r < nr; r++) {
+  // one wave per request: scan the partner segment, minimum key by shuffles
+  // (keys end in the partner id, so they are distinct)
+  for (int r = tid >> 6; r < nr; r += TAIL_TPB / 64) {
     const Request<R> q = D.req[r];
     const int t = (q.chan == 13) ? 1 : 2;
     const int32_t lo = D.seg[t * (N + 1) + q.cell], hi = D.seg[t * (N + 1) + q.cell + 1];
     uint64_t best = ~0ull;
     int32_t bslot = -1;
-    for (int32_t i = lo + tid; i < hi; i += TAIL_TPB) {
+    for (int32_t i = lo + lane; i < hi; i += 64) {
       const uint64_t k = pick_key(C, D.st[t].id[i], q.id, n);
       if (k < best) {
         best = k;
         bslot = i;
       }
     }
-    bk[tid] = best;
-    bi[tid] = bslot;
-    __syncthreads();
-    for (int d = TAIL_TPB / 2; d > 0; d >>= 1) {
-      if (tid < d && bk[tid + d] < bk[tid]) {
-        bk[tid] = bk[tid + d];
-        bi[tid] = bi[tid + d];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const uint64_t ok = __shfl_xor(best, d);
+      const int32_t os = __shfl_xor(bslot, d);
+      if (ok < best) {
+        best = ok;
+        bslot = os;
       }
-      __syncthreads();
     }
-    if (tid == 0) {
-      const int32_t p = bi[0];
+    if (lane == 0) {
+      const int32_t p = bslot;
       int acc = 0;
       if (p >= 0 && D.st[t].cell[p] != DEAD) {
         const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
@@ -1108,8 +1140,8 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
       L.racc[r] = (uint8_t)acc;
       L.rwin[r] = 0;
     }
-    __syncthreads();
   }
+  __syncthreads();
   // stage 1: electron test particles; (13) takes an O2+, (19) an O-
   for (int r = tid; r < nr; r += TAIL_TPB) {
     const int chan = D.req[r].chan;
@@ -1213,6 +1245,31 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
 //  3. close the step (store lengths, id counter, rf-cycle sums);
 //  4. unless a sort follows, the field of step n+1.
 // ---------------------------------------------------------------------------
+// exclusive prefix sum of one value per thread over a workgroup of TPB
+// threads (shuffles inside waves, wsum[TPB/64] in LDS across them)
+template <int TPB>
+__device__ __forceinline__ int block_excl_scan(int x, int32_t* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; w++) {
+    const int v = wsum[w];
+    if (w < wv) base += v;
+    tot += v;
+  }
+  *total = tot;
+  __syncthreads();
+  return base + incl - x;
+}
+
 template <class R>
 __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, int32_t* part) {
   const int tid = threadIdx.x;
@@ -1220,32 +1277,30 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
   if (B > D.nb_cap) B = D.nb_cap;
   if (B == 0) return;
   constexpr int PER = NBUCKET / TAIL_TPB;
+  // bucket counts to LDS (coalesced), exclusive scan over consecutive
+  // buckets per thread, offsets back to global memory (coalesced)
+  for (int i = tid; i < NBUCKET; i += TAIL_TPB) {
+    cur[i] = D.bhist[i];
+    D.bhist[i] = 0;
+  }
+  __syncthreads();
   int loc[PER];
   int sum = 0;
 #pragma unroll
   for (int q = 0; q < PER; q++) {
-    loc[q] = D.bhist[tid * PER + q];
+    loc[q] = cur[tid * PER + q];
     sum += loc[q];
   }
-#pragma unroll
-  for (int q = 0; q < PER; q++) D.bhist[tid * PER + q] = 0;
-  part[tid] = sum;
-  __syncthreads();
-  for (int d = 1; d < TAIL_TPB; d <<= 1) {
-    const int x = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += x;
-    __syncthreads();
-  }
-  int run = part[tid] - sum;
+  int total;
+  int run = block_excl_scan<TAIL_TPB>(sum, part, &total);
 #pragma unroll
   for (int q = 0; q < PER; q++) {
-    D.boff[tid * PER + q] = run;
     cur[tid * PER + q] = run;
     run += loc[q];
   }
-  if (tid == TAIL_TPB - 1) D.boff[NBUCKET] = run;
+  if (tid == 0) D.boff[NBUCKET] = total;
   __syncthreads();
+  for (int i = tid; i < NBUCKET; i += TAIL_TPB) D.boff[i] = cur[i];
   const uint64_t next = (uint64_t)D.ctr->next_id;
   for (int b = tid; b < B; b += TAIL_TPB) {
     const int bkt = birth_bucket(D.nb[b].creator, next);
@@ -1283,11 +1338,7 @@ template <class R, int PER>
 __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int do_field) {
   __shared__ union {
     FieldLds field;
-    struct {
-      ClaimLds L;
-      uint64_t bk[TAIL_TPB];
-      int32_t bi[TAIL_TPB];
-    } claims;
+    ClaimLds claims;
     int32_t cur[NBUCKET];
   } U;
   __shared__ int32_t part[TAIL_TPB];
@@ -1295,7 +1346,7 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
   const int64_t n = D.ctr->step;
   int nr = *D.nreq;
   if (nr > D.req_cap) nr = D.req_cap;
-  if (nr > 0) resolve_claims(C, D, U.claims.L, U.claims.bk, U.claims.bi, nr, (uint32_t)n);
+  if (nr > 0) resolve_claims(C, D, U.claims, nr, (uint32_t)n);
   __threadfence();
   __syncthreads();
   births_phase(C, D, U.cur, part);
