@@ -76,6 +76,7 @@ def lib(prec: str = "fp32"):
                                  P(C.c_double), P(C.c_double)]
     L.or_log_enable.argtypes = [C.c_void_p, C.c_int64]
     L.or_scale_velocities.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
+    L.or_math.argtypes = [P(C.c_double), C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double)]
     L.or_log_read.restype = C.c_int64
     L.or_log_read.argtypes = [C.c_void_p, P(C.c_double), C.c_int64]
     _loaded[prec] = L
@@ -93,6 +94,14 @@ def philox(ctr, key, prec="fp32"):
     o = (C.c_uint32 * 4)()
     L.or_philox(c, k, o)
     return list(o)
+
+
+def math(u, prec="fp32"):
+    """The sampler's sin(2 pi u), cos(2 pi u) and ln(u) of the oracle."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    sn, cs, lg = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+    lib(prec).or_math(_ptr(u, C.c_double), len(u), _ptr(sn, C.c_double), _ptr(cs, C.c_double), _ptr(lg, C.c_double))
+    return sn, cs, lg
 
 
 def solve_field(q, dx, cphi, cE, U0, prec="fp64"):

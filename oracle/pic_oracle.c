@@ -107,9 +107,116 @@ static double unif52(uint32_t a, uint32_t b) {
   return ((double)m + 0.5) * 0x1p-52;
 }
 
-static real bm_radius(real u) { return (real)sqrt(-2.0 * log((double)u)); }
-static real cos2pi(real u) { return (real)cos(TWO_PI * (double)u); }
-static real sin2pi(real u) { return (real)sin(TWO_PI * (double)u); }
+/* ----------------------------------------------------------------------- */
+/* elementary functions of the samplers, in the working precision           */
+/*                                                                          */
+/* sin and cos of 2 pi u: u = (k + f)/4 with |f| <= 1/2, Taylor series of   */
+/* sin(pi f / 2) and cos(pi f / 2) in f (6/7 terms in float, 10/11 in       */
+/* double), then the quadrant k.  ln u: u = m 2^e with m in [1/sqrt2,       */
+/* sqrt2), ln m = 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ...), s = (m-1)/    */
+/* (m+1) (6 terms in float, 12 in double).  Fixed term counts and Horner    */
+/* order, so the result is a fixed sequence of IEEE operations.  The        */
+/* coefficients are formed in double and rounded once.                      */
+/* ----------------------------------------------------------------------- */
+#ifdef ORACLE_FP64
+#define NSIN 10
+#define NCOS 11
+#define NLOG 12
+#else
+#define NSIN 6
+#define NCOS 7
+#define NLOG 6
+#endif
+static real SINC[NSIN], COSC[NCOS], LOGC[NLOG], LN2R, SQRT2R;
+
+static void init_series(void) {
+  const double h = 1.5707963267948966; /* pi / 2 */
+  const double t = h * h;
+  double c = h, d = 1.0;
+  for (int j = 0; j < NSIN; j++) {
+    SINC[j] = (real)c;
+    c = (c * -t) / (double)((2 * j + 2) * (2 * j + 3));
+  }
+  for (int j = 0; j < NCOS; j++) {
+    COSC[j] = (real)d;
+    d = (d * -t) / (double)((2 * j + 1) * (2 * j + 2));
+  }
+  for (int k = 0; k < NLOG; k++) LOGC[k] = (real)(1.0 / (double)(2 * k + 1));
+  LN2R = (real)0.6931471805599453;
+  SQRT2R = (real)1.4142135623730951;
+}
+
+static void sincos2pi(real u, real* sn, real* cs) {
+  real x = u * (real)4;
+  int k = (int)x;
+  real f = x - (real)k;
+  if (f > (real)0.5) {
+    f = f - (real)1;
+    k = k + 1;
+  }
+  real z = f * f;
+  real ps = SINC[NSIN - 1];
+  for (int j = NSIN - 2; j >= 0; j--) ps = ps * z + SINC[j];
+  real s = f * ps;
+  real pc = COSC[NCOS - 1];
+  for (int j = NCOS - 2; j >= 0; j--) pc = pc * z + COSC[j];
+  switch (k & 3) {
+    case 0: *sn = s; *cs = pc; break;
+    case 1: *sn = pc; *cs = -s; break;
+    case 2: *sn = -s; *cs = -pc; break;
+    default: *sn = -pc; *cs = s; break;
+  }
+}
+
+static real plog(real u) {
+  int e;
+  real m;
+#ifdef ORACLE_FP64
+  uint64_t b;
+  memcpy(&b, &u, 8);
+  e = (int)((b >> 52) & 0x7FF) - 1023;
+  b = (b & 0xFFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+  memcpy(&m, &b, 8);
+#else
+  uint32_t b;
+  memcpy(&b, &u, 4);
+  e = (int)((b >> 23) & 0xFF) - 127;
+  b = (b & 0x7FFFFFu) | 0x3F800000u;
+  memcpy(&m, &b, 4);
+#endif
+  if (m > SQRT2R) {
+    m = m * (real)0.5;
+    e = e + 1;
+  }
+  real s = (m - (real)1) / (m + (real)1);
+  real z = s * s;
+  real p = LOGC[NLOG - 1];
+  for (int k = NLOG - 2; k >= 0; k--) p = p * z + LOGC[k];
+  return (real)e * LN2R + (s + s) * p;
+}
+
+static real bm_radius(real u) { return RSQRT((real)-2 * plog(u)); }
+static real cos2pi(real u) {
+  real s, c;
+  sincos2pi(u, &s, &c);
+  return c;
+}
+static real sin2pi(real u) {
+  real s, c;
+  sincos2pi(u, &s, &c);
+  return s;
+}
+
+void or_math(const double* u, int64_t n, double* sn, double* cs, double* lg) {
+  init_series();
+  for (int64_t i = 0; i < n; i++) {
+    real s, c;
+    sincos2pi((real)u[i], &s, &c);
+    sn[i] = (double)s;
+    cs[i] = (double)c;
+    lg[i] = (double)plog((real)u[i]);
+  }
+}
 
 /* isotropic unit vector: cos(theta) = 1 - 2u, phi = 2 pi u' */
 static void iso_dir(uint32_t wc, uint32_t wp, real n[3]) {
@@ -377,6 +484,7 @@ static double pmax_of(const or_ctx* c, int s) {
 }
 
 or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, const double* loss, int* err) {
+  init_series();
   *err = OR_OK;
   if (p->n_cells < 4 || p->gap_m <= 0 || p->area_m2 <= 0 || p->weight <= 0 || p->steps_per_period < 1 ||
       p->ion_subcycle < 1 || p->sort_every < 1 || p->frequency_Hz <= 0 || p->coulomb_every < 0 ||
@@ -865,7 +973,8 @@ static int ckey_cmp(const void* x, const void* y) {
 }
 
 /* one binary collision of A and B (equal masses); cc = Eq. (2) prefactor times the
-   particle count m of the cell; randoms from Philox(rid, n, k) */
+   particle count m of the cell; randoms from Philox with counter (rid_lo, rid_hi, n, k),
+   where rid = (s N + cell) 2^32 + rank of A in the cell's pairing order */
 static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k,
                        int sp, int64_t m, int half) {
   real ux = A->v[0] - B->v[0], uy = A->v[1] - B->v[1], uz = A->v[2] - B->v[2];
@@ -954,18 +1063,19 @@ static void coulomb(or_ctx* c, uint32_t n) {
       if (m < 2) continue;
       ckey* K = keys + start[cc];
       qsort(K, (size_t)m, sizeof(ckey), ckey_cmp);
+      const uint64_t key = (uint64_t)(s * N + cc) << 32;
       int64_t first = 0;
       if (m % 2 == 1) {  /* odd: the first three collide pairwise with half the interval */
         real ch = c->cc_coul_half[s] * (real)m;
         part *a = &S->a[K[0].idx], *b = &S->a[K[1].idx], *d = &S->a[K[2].idx];
-        ta_collide(c, a, b, ch, K[0].id, n, 17, s, m, 1);
-        ta_collide(c, b, d, ch, K[1].id, n, 18, s, m, 1);
-        ta_collide(c, d, a, ch, K[2].id, n, 19, s, m, 1);
+        ta_collide(c, a, b, ch, key | 0, n, 17, s, m, 1);
+        ta_collide(c, b, d, ch, key | 1, n, 18, s, m, 1);
+        ta_collide(c, d, a, ch, key | 2, n, 19, s, m, 1);
         first = 3;
       }
       real cf = c->cc_coul[s] * (real)m;
       for (int64_t q = first; q + 1 < m; q += 2)
-        ta_collide(c, &S->a[K[q].idx], &S->a[K[q + 1].idx], cf, K[q].id, n, 17, s, m, 0);
+        ta_collide(c, &S->a[K[q].idx], &S->a[K[q + 1].idx], cf, key | (uint64_t)q, n, 17, s, m, 0);
     }
     free(start);
     free(keys);

@@ -78,6 +78,8 @@ double or_sigma(const or_ctx* c, int chan, double E_eV);   /* table interpolatio
 /* Poisson solve of the discrete Dirichlet problem from integer net charge q[0..N] */
 void or_solve_field(int32_t N, double dx, double cphi, double cE, double U0, const int64_t* q,
                     double* phi, double* E);
+/* the sampler's sin(2 pi u), cos(2 pi u) and ln u in the working precision, for n points u */
+void or_math(const double* u, int64_t n, double* sn, double* cs, double* lg);
 /* test hook: multiply velocity component d of every particle of species sp by f[d] */
 void or_scale_velocities(or_ctx* c, int sp, const double f[3]);
 /* event log: enable with capacity; entries of 16 doubles (see source) */

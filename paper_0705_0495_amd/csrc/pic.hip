@@ -113,7 +113,7 @@ struct Impl : Base {
   Consts<R> C;
   Dev<R> D;
   std::vector<void*> allocs;
-  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0, grid_coulomb = 0;
+  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0, ncu = 1;
   int64_t nstep = 0;  // steps enqueued
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
@@ -221,6 +221,23 @@ struct Impl : Base {
     C.eedf_sc = (R)(G.eedf_bins > 0 ? (double)G.eedf_bins / G.eedf_emax_eV : 0.0);
     C.fneg_sc = (R)(G.fneg_ebins > 0 ? (double)G.fneg_ebins / (2.0 * G.fneg_emax_eV) : 0.0);
     C.fneg_em = (R)G.fneg_emax_eV;
+    // series of the samplers' sin, cos and ln: coefficients in double, rounded once
+    {
+      const double h = 1.5707963267948966;  // pi / 2
+      const double t = h * h;
+      double cs = h, cc = 1.0;
+      for (int j = 0; j < Series<R>::NS; j++) {
+        C.sinc[j] = (R)cs;
+        cs = (cs * -t) / (double)((2 * j + 2) * (2 * j + 3));
+      }
+      for (int j = 0; j < Series<R>::NC; j++) {
+        C.cosc[j] = (R)cc;
+        cc = (cc * -t) / (double)((2 * j + 1) * (2 * j + 2));
+      }
+      for (int k = 0; k < Series<R>::NL; k++) C.logc[k] = (R)(1.0 / (double)(2 * k + 1));
+      C.ln2 = (R)0.6931471805599453;
+      C.sqrt2 = (R)1.4142135623730951;
+    }
     // Eq. (2) with eps0^2 and the reduced mass mu = m/2 of like particles; the
     // density is W * (particles in the cell) / (A dx), t_c2 = coulomb_every dt
     const double PI_H = 3.141592653589793;
@@ -273,7 +290,7 @@ struct Impl : Base {
     if ((rc = alloc(&D.perm, (size_t)D.nb_cap))) return rc;
     for (int s = 0; s < 3; s++) {
       if ((rc = alloc(&D.cand[s], (size_t)D.cap[s] + TILE))) return rc;
-      if ((rc = alloc(&D.tcnt[s], (size_t)(D.cap[s] / TILE + 2)))) return rc;
+      if ((rc = alloc(&D.tcnt[s], (size_t)(D.cap[s] / WTILE + 8)))) return rc;
     }
     if ((rc = alloc(&D.ncand, 3))) return rc;
     D.req_cap = REQ_CAP;
@@ -290,6 +307,8 @@ struct Impl : Base {
     if ((rc = alloc(&D.fneg_acc, (size_t)FNEG_MAX))) return rc;
     if ((rc = alloc(&D.fneg_last, (size_t)FNEG_MAX))) return rc;
     if ((rc = alloc(&D.done, 4))) return rc;
+    if ((rc = alloc(&D.ncoul, 1))) return rc;
+    if ((rc = alloc(&D.coul_big, 3 * (size_t)N))) return rc;
 
     // drive table and cross-section table (host math, uploaded once)
     std::vector<double> U(G.steps_per_period);
@@ -307,14 +326,14 @@ struct Impl : Base {
     HIPCHK(c, hipMemcpyAsync(D.N, G.n_init, sizeof(int64_t) * 3, hipMemcpyHostToDevice, c->stream));
 
     // launch shapes
-    int dev = 0, ncu = 0, occ = 0;
+    int dev = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
     grid_scatter = std::max(1, ncu * 4);
     grid_collide = std::max(1, ncu * 8);
-    grid_coulomb = 3 * N;  // one workgroup per (species, cell); 147 KB of LDS each
+
 
     // initial load, deposit, field at t = 0, half step back, first sort
     const int64_t tot = G.n_init[0] + G.n_init[1] + G.n_init[2];
@@ -378,9 +397,7 @@ struct Impl : Base {
         if (rc) return rc;
         const int ce = c->G.coulomb_every;
         if (ce > 0 && nstep % ce == 0) {
-          hipLaunchKernelGGL(k_coulomb<R>, dim3(grid_coulomb), dim3(COUL_TPB), 0, c->stream, C, D,
-                             (uint32_t)(nstep - 1));
-          HIPCHK(c, hipGetLastError());
+          HIPCHK(c, launch_coulomb(C, D, (uint32_t)(nstep - 1), ncu, c->stream));
         }
         HIPCHK(c, launch_field(C, D, 1, c->stream));
       }

@@ -21,6 +21,7 @@ constexpr int32_t DEAD = INT32_MIN;
 constexpr int TPB = 256;               // threads per push workgroup
 constexpr int PPT = 4;                 // consecutive particles per thread (16-byte vectors)
 constexpr int TILE = TPB * PPT;
+constexpr int WTILE = 64 * PPT;        // one wave's part of a tile
 constexpr int WIN = 512;               // cells of the LDS deposit window
 constexpr int EEDF_MAX = 256;
 constexpr int FNEG_MAX = 2048;
@@ -52,7 +53,13 @@ struct Consts {
   int32_t eedf_bins, fneg_xbins, fneg_ebins, pad;
   R eedf_sc, fneg_sc, fneg_em;
   R ccoul[3], ccoul_h[3];   // Eq. (2) prefactor per particle in the cell: full and half interval
+  R sinc[10], cosc[11], logc[12], ln2, sqrt2;  // series of the samplers' elementary functions
 };
+
+// terms of the elementary-function series per precision
+template <class R> struct Series;
+template <> struct Series<float> { static constexpr int NS = 6, NC = 7, NL = 6; };
+template <> struct Series<double> { static constexpr int NS = 10, NC = 11, NL = 12; };
 
 struct Counters {
   int64_t step, next_id;
@@ -136,7 +143,8 @@ struct Dev {
   int32_t* boff;    // [NBUCKET+1]
   int32_t* perm;    // [nb_cap] births grouped by bucket
   Cand<R>* cand[3]; // candidates of the null-collision test: tile t of species s
-                    // writes them to cand[s][t*TILE ...]
+                    // writes them to cand[s][t*TILE ...], wave w of the
+                    // tile to cand[s][t*TILE + w*WTILE ...], count in tcnt[s][t*TILE/WTILE + w]
   int32_t* tcnt[3]; // candidates per tile
   int32_t* ncand;   // [3] (unused)
   Request<R>* req;
@@ -152,6 +160,8 @@ struct Dev {
   int64_t* fneg_acc;
   int64_t* fneg_last;
   uint32_t* done;   // [4] last-workgroup counters
+  int32_t* ncoul;   // cells above COUL_SMALL particles in this Coulomb pass
+  int32_t* coul_big;  // [3 Nc] their (species, cell) indices
 };
 
 // ---------------------------------------------------------------------------
@@ -197,18 +207,89 @@ __device__ __forceinline__ float Floor(float x) { return floorf(x); }
 __device__ __forceinline__ double Floor(double x) { return floor(x); }
 
 // samplers: transcendentals in double, rounded once to R
-template <class R> __device__ __forceinline__ R bm_radius(R u) { return (R)sqrt(-2.0 * log((double)u)); }
-template <class R> __device__ __forceinline__ R cos2pi(R u) { return (R)cos(TWO_PI * (double)u); }
-template <class R> __device__ __forceinline__ R sin2pi(R u) { return (R)sin(TWO_PI * (double)u); }
+// sin and cos of 2 pi u for u in (0,1): u = (k + f)/4 with |f| <= 1/2, Taylor
+// series of sin(pi f/2) and cos(pi f/2) in f with a fixed number of terms in
+// Horner order, then the quadrant k.  ln u for u > 0: u = m 2^e with m in
+// [1/sqrt2, sqrt2), ln m = 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ...),
+// s = (m-1)/(m+1).  The coefficients are formed on the host in double and
+// rounded once (Consts::sinc, cosc, logc).
+template <class R>
+__device__ __forceinline__ void sincos2pi(const Consts<R>& C, R u, R& sn, R& cs) {
+  const R x = u * (R)4;
+  int k = (int)x;
+  R f = x - (R)k;
+  if (f > (R)0.5) {
+    f = f - (R)1;
+    k = k + 1;
+  }
+  const R z = f * f;
+  R ps = C.sinc[Series<R>::NS - 1];
+#pragma unroll
+  for (int j = Series<R>::NS - 2; j >= 0; j--) ps = ps * z + C.sinc[j];
+  const R s = f * ps;
+  R pc = C.cosc[Series<R>::NC - 1];
+#pragma unroll
+  for (int j = Series<R>::NC - 2; j >= 0; j--) pc = pc * z + C.cosc[j];
+  switch (k & 3) {
+    case 0: sn = s; cs = pc; break;
+    case 1: sn = pc; cs = -s; break;
+    case 2: sn = -s; cs = -pc; break;
+    default: sn = -pc; cs = s; break;
+  }
+}
+
+__device__ __forceinline__ void split_exp(float u, float& m, int& e) {
+  const uint32_t b = __float_as_uint(u);
+  e = (int)((b >> 23) & 0xFFu) - 127;
+  m = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+}
+__device__ __forceinline__ void split_exp(double u, double& m, int& e) {
+  const uint64_t b = (uint64_t)__double_as_longlong(u);
+  e = (int)((b >> 52) & 0x7FFull) - 1023;
+  m = __longlong_as_double((long long)((b & 0xFFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+}
 
 template <class R>
-__device__ __forceinline__ void iso_dir(uint32_t wc, uint32_t wp, R n[3]) {
+__device__ __forceinline__ R plog(const Consts<R>& C, R u) {
+  R m;
+  int e;
+  split_exp(u, m, e);
+  if (m > C.sqrt2) {
+    m = m * (R)0.5;
+    e = e + 1;
+  }
+  const R s = (m - (R)1) / (m + (R)1);
+  const R z = s * s;
+  R p = C.logc[Series<R>::NL - 1];
+#pragma unroll
+  for (int k = Series<R>::NL - 2; k >= 0; k--) p = p * z + C.logc[k];
+  return (R)e * C.ln2 + (s + s) * p;
+}
+
+template <class R> __device__ __forceinline__ R bm_radius(const Consts<R>& C, R u) {
+  return Sqrt((R)-2 * plog<R>(C, u));
+}
+template <class R> __device__ __forceinline__ R cos2pi(const Consts<R>& C, R u) {
+  R s, c;
+  sincos2pi<R>(C, u, s, c);
+  return c;
+}
+template <class R> __device__ __forceinline__ R sin2pi(const Consts<R>& C, R u) {
+  R s, c;
+  sincos2pi<R>(C, u, s, c);
+  return s;
+}
+
+template <class R>
+__device__ __forceinline__ void iso_dir(const Consts<R>& C, uint32_t wc, uint32_t wp, R n[3]) {
   R u = unif<R>(wc);
   R ct = (R)1 - (R)2 * u;
   R st = Sqrt((R)1 - ct * ct);
   R up = unif<R>(wp);
-  n[0] = st * cos2pi<R>(up);
-  n[1] = st * sin2pi<R>(up);
+  R sp, cp;
+  sincos2pi<R>(C, up, sp, cp);
+  n[0] = st * cp;
+  n[1] = st * sp;
   n[2] = ct;
 }
 
@@ -613,8 +694,8 @@ __device__ __forceinline__ bool gas_event(const Consts<R>& C, const Dev<R>& D, i
                           const R vt[3], R g, R Erel, uint32_t n) {
   const uint4 w = rng(C, id, n, 2);
   R n1[3], n2[3];
-  iso_dir<R>(w.x, w.y, n1);
-  iso_dir<R>(w.z, w.w, n2);
+  iso_dir<R>(C, w.x, w.y, n1);
+  iso_dir<R>(C, w.z, w.w, n2);
   const R a = C.a_g[S], b = C.b_g[S];
   R vc[3];
 #pragma unroll
@@ -702,12 +783,12 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
   }
   // gas target drawn from the Maxwellian at T_gas
   const uint4 u = rng(C, id, n, 1);
-  const R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
-  const R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
+  const R r1 = bm_radius<R>(C, unif<R>(u.x)), a1 = unif<R>(u.y);
+  const R r2 = bm_radius<R>(C, unif<R>(u.z)), a2 = unif<R>(u.w);
   R vt[3];
-  vt[0] = C.vthg * (r1 * cos2pi<R>(a1));
-  vt[1] = C.vthg * (r1 * sin2pi<R>(a1));
-  vt[2] = C.vthg * (r2 * cos2pi<R>(a2));
+  vt[0] = C.vthg * (r1 * cos2pi<R>(C, a1));
+  vt[1] = C.vthg * (r1 * sin2pi<R>(C, a1));
+  vt[2] = C.vthg * (r2 * cos2pi<R>(C, a2));
   const R gx = v[0] - vt[0], gy = v[1] - vt[1], gz = v[2] - vt[2];
   const R g2 = (gx * gx + gy * gy) + gz * gz;
   const R g = Sqrt(g2);
@@ -740,26 +821,33 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
 }
 
 constexpr int COLL_TPB = 256;
-constexpr int COLL_GROUP = 8;  // tiles per workgroup iteration
+constexpr int COLL_GROUP = 32;  // candidate regions (one per push wave) per workgroup iteration
 
 template <class R, int S>
 __device__ __forceinline__ void collide_group(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int32_t* pre,
-                                              int64_t tile0, int64_t ntiles, uint32_t n) {
+                                              int64_t reg0, int64_t nreg, uint32_t n) {
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    int run = 0;
-    for (int k = 0; k < COLL_GROUP; k++) {
-      pre[k] = run;
-      run += (tile0 + k < ntiles) ? D.tcnt[S][tile0 + k] : 0;
+  if (tid < 64) {
+    // inclusive scan of the group's candidate counts in the first wave
+    int x = (tid < COLL_GROUP && reg0 + tid < nreg) ? D.tcnt[S][reg0 + tid] : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (tid >= d) x += y;
     }
-    pre[COLL_GROUP] = run;
+    if (tid < COLL_GROUP) pre[tid + 1] = x;
+    if (tid == 0) pre[0] = 0;
   }
   __syncthreads();
   const int tot = pre[COLL_GROUP];
   for (int e = tid; e < tot; e += COLL_TPB) {
-    int k = 0;
-    while (e >= pre[k + 1]) k++;
-    collide_one<R, S>(C, D, G, (tile0 + k) * TILE + (e - pre[k]), n);
+    int lo = 0, hi = COLL_GROUP;  // the region k with pre[k] <= e < pre[k+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    collide_one<R, S>(C, D, G, (reg0 + lo) * WTILE + (e - pre[lo]), n);
   }
   __syncthreads();
 }
@@ -776,7 +864,7 @@ __global__ void __launch_bounds__(COLL_TPB) k_collide(Consts<R> C, Dev<R> D) {
   int64_t nt[3], ng[3];
   for (int s = 0; s < 3; s++) {
     const int64_t Ns = (s == 0 || ion) ? D.N[s] : 0;
-    nt[s] = (Ns + TILE - 1) / TILE;
+    nt[s] = (Ns + WTILE - 1) / WTILE;
     ng[s] = (nt[s] + COLL_GROUP - 1) / COLL_GROUP;
   }
   const int64_t total = ng[0] + ng[1] + ng[2];
@@ -793,10 +881,8 @@ __global__ void __launch_bounds__(COLL_TPB) k_collide(Consts<R> C, Dev<R> D) {
 // ---------------------------------------------------------------------------
 template <class R>
 struct PushLds {
-  uint64_t win[WIN];
+  uint64_t win[2][WIN];  // deposit windows of consecutive tiles (alternating)
   DiagLds G;
-  int32_t base;
-  int32_t ncand;
 };
 
 template <class R> struct Vec4;
@@ -821,15 +907,14 @@ template <> struct Vec4<double> {
 };
 
 // add a packed (count << 40 | sum of 24-bit fractions) to one cell
-template <class R>
-__device__ __forceinline__ void deposit_win(PushLds<R>& L, const Dev<R>& D, int N, int sp, int base, int cell,
+__device__ __forceinline__ void deposit_win(uint64_t* win, int32_t* cnt, int64_t* F, int base, int cell,
                                             uint64_t packed) {
   const int idx = cell - base;
   if ((unsigned)idx < (unsigned)WIN) {
-    atomicAdd((unsigned long long*)&L.win[idx], (unsigned long long)packed);
+    atomicAdd((unsigned long long*)&win[idx], (unsigned long long)packed);
   } else {
-    atomicAdd(&D.cnt[(size_t)sp * N + cell], (int)(packed >> 40));
-    atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)(packed & F_MASK));
+    atomicAdd(&cnt[cell], (int)(packed >> 40));
+    atomicAdd((unsigned long long*)&F[cell], (unsigned long long)(packed & F_MASK));
   }
 }
 
@@ -837,37 +922,43 @@ struct TileCount {
   int pushed, abs0, abs1;
 };
 
+// One workgroup pushes one tile of TILE consecutive particles.  Deposits go
+// to an LDS window of WIN cells (one 64-bit LDS atomic per run of a thread's
+// particles in one cell), flushed to global memory after the tile's single
+// barrier; consecutive tiles alternate between two windows, so the next tile
+// starts while this one is flushed.  Each wave writes its candidates to its
+// own region of the list.
 template <class R, int S>
-__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int64_t t0,
-                                               int64_t Ns, uint32_t n, uint64_t T0, double pmax) {
+__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int buf,
+                                               int64_t t0, int64_t Ns, uint32_t n, uint64_t T0, double pmax) {
   TileCount tc = {0, 0, 0};
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int N = C.N;
   const Store<R> st = D.st[S];
-  if (tid == 0) {
-    const int32_t c0 = st.cell[t0];
-    L.base = (c0 == DEAD ? 0 : c0) - 64;
-    L.ncand = 0;
-  }
-  for (int i = tid; i < WIN; i += TPB) L.win[i] = 0;
-  __syncthreads();
-  const int base = L.base;
+  int32_t* cnt_s = D.cnt + (size_t)S * N;
+  int64_t* F_s = D.F + (size_t)S * N;
+  uint64_t* win = L.win[buf];
+  const int32_t cfirst = st.cell[t0];
+  const int base = (cfirst == DEAD ? 0 : cfirst) - 64;
   const int64_t s0 = t0 + (int64_t)PPT * tid;
-  int32_t c[4];
-  R off[4], vx[4];
-  uint64_t id[4];
-  const bool full = s0 + 3 < Ns;
+  int32_t c[PPT];
+  R off[PPT], vx[PPT];
+  uint64_t id[PPT];
+  const bool full = s0 + PPT - 1 < Ns;
   if (full) {
-    const int4 cv = *(const int4*)(st.cell + s0);
-    c[0] = cv.x; c[1] = cv.y; c[2] = cv.z; c[3] = cv.w;
-    Vec4<R>::load(st.off + s0, off);
-    Vec4<R>::load(st.vx + s0, vx);
-    const ulonglong2 ia = *(const ulonglong2*)(st.id + s0), ib = *(const ulonglong2*)(st.id + s0 + 2);
-    id[0] = ia.x; id[1] = ia.y; id[2] = ib.x; id[3] = ib.y;
+#pragma unroll
+    for (int h = 0; h < PPT; h += 4) {
+      const int4 cv = *(const int4*)(st.cell + s0 + h);
+      c[h] = cv.x; c[h + 1] = cv.y; c[h + 2] = cv.z; c[h + 3] = cv.w;
+      Vec4<R>::load(st.off + s0 + h, off + h);
+      Vec4<R>::load(st.vx + s0 + h, vx + h);
+      const ulonglong2 ia = *(const ulonglong2*)(st.id + s0 + h), ib = *(const ulonglong2*)(st.id + s0 + h + 2);
+      id[h] = ia.x; id[h + 1] = ia.y; id[h + 2] = ib.x; id[h + 3] = ib.y;
+    }
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < PPT; q++) {
       const bool in = s0 + q < Ns;
       c[q] = in ? st.cell[s0 + q] : DEAD;
       off[q] = in ? st.off[s0 + q] : (R)0;
@@ -875,13 +966,15 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       id[q] = in ? st.id[s0 + q] : 0;
     }
   }
-  const bool was_dead[4] = {c[0] == DEAD, c[1] == DEAD, c[2] == DEAD, c[3] == DEAD};
+  bool was_dead[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; q++) was_dead[q] = c[q] == DEAD;
   int candmask = 0;
   // a thread's consecutive particles mostly share a cell: one atomic per run
   int run_cell = -1;
   uint64_t run_val = 0;
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
+  for (int q = 0; q < PPT; q++) {
     if (was_dead[q]) continue;
     tc.pushed++;
     const R E0 = D.E2[2 * c[q]], E1 = D.E2[2 * c[q] + 1];
@@ -917,7 +1010,7 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
     }
     c[q] = cn;
     if (cn != run_cell) {
-      if (run_cell >= 0) deposit_win(L, D, N, S, base, run_cell, run_val);
+      if (run_cell >= 0) deposit_win(win, cnt_s, F_s, base, run_cell, run_val);
       run_cell = cn;
       run_val = 0;
     }
@@ -935,14 +1028,17 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       diag_alive<R, S>(C, L.G, cn, vx[q], (R)0, (R)0);
     }
   }
-  if (run_cell >= 0) deposit_win(L, D, N, S, base, run_cell, run_val);
+  if (run_cell >= 0) deposit_win(win, cnt_s, F_s, base, run_cell, run_val);
   if (full) {
-    *(int4*)(st.cell + s0) = make_int4(c[0], c[1], c[2], c[3]);
-    Vec4<R>::store(st.off + s0, off);
-    Vec4<R>::store(st.vx + s0, vx);
+#pragma unroll
+    for (int h = 0; h < PPT; h += 4) {
+      *(int4*)(st.cell + s0 + h) = make_int4(c[h], c[h + 1], c[h + 2], c[h + 3]);
+      Vec4<R>::store(st.off + s0 + h, off + h);
+      Vec4<R>::store(st.vx + s0 + h, vx + h);
+    }
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < PPT; q++) {
       if (s0 + q < Ns && !was_dead[q]) {
         st.cell[s0 + q] = c[q];
         st.off[s0 + q] = off[q];
@@ -950,8 +1046,7 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       }
     }
   }
-  // candidates go to this tile's own region of the list: a wave prefix sum
-  // and one LDS atomic per wave, no global atomics
+  // candidates go to the wave's own region of the list (its 256 slots)
   const int mine = __popc(candmask);
   int incl = mine;
 #pragma unroll
@@ -959,13 +1054,10 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
     const int y = __shfl_up(incl, d);
     if (lane >= d) incl += y;
   }
-  const int wtot = __shfl(incl, 63);
-  int wbase = 0;
-  if (lane == 63 && wtot > 0) wbase = atomicAdd(&L.ncand, wtot);
-  wbase = __shfl(wbase, 63);
-  int pos = wbase + incl - mine;
+  const int64_t r0 = t0 + (int64_t)(tid >> 6) * WTILE;
+  int pos = incl - mine;
 #pragma unroll
-  for (int q = 0; q < 4; q++)
+  for (int q = 0; q < PPT; q++)
     if (candmask & (1 << q)) {
       Cand<R> k;
       k.slot = (int32_t)(s0 + q);
@@ -973,21 +1065,19 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       k.off = off[q];
       k.vx = vx[q];
       k.id = id[q];
-      D.cand[S][t0 + pos++] = k;
+      D.cand[S][r0 + pos++] = k;
     }
+  if (lane == 63) D.tcnt[S][r0 / WTILE] = incl;
   __syncthreads();
-  if (tid == 0) D.tcnt[S][t0 / TILE] = L.ncand;
-  int32_t* cnt_s = D.cnt + (size_t)S * N;
-  int64_t* F_s = D.F + (size_t)S * N;
   for (int i = tid; i < WIN; i += TPB) {
-    const uint64_t v = L.win[i];
+    const uint64_t v = win[i];
     if (v) {
       const int cc = base + i;
       atomicAdd(&cnt_s[cc], (int)(v >> 40));
       atomicAdd((unsigned long long*)&F_s[cc], (unsigned long long)(v & F_MASK));
+      win[i] = 0;
     }
   }
-  __syncthreads();
   return tc;
 }
 
@@ -1011,6 +1101,7 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
   diag_init(L.G);
+  for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
   __syncthreads();
   int64_t Ns[3], nt[3];
   double pm[3];
@@ -1025,15 +1116,16 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   }
   const int64_t total = nt[0] + nt[1] + nt[2];
   int ps = 0, ae0 = 0, ae1 = 0, an0 = 0, an1 = 0, ap0 = 0, ap1 = 0;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  int buf = 0;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x, buf ^= 1) {
     if (t < nt[0]) {
-      const TileCount k = push_tile<R, 0>(C, D, L, t * TILE, Ns[0], n, T0[0], pm[0]);
+      const TileCount k = push_tile<R, 0>(C, D, L, buf, t * TILE, Ns[0], n, T0[0], pm[0]);
       ps += k.pushed; ae0 += k.abs0; ae1 += k.abs1;
     } else if (t < nt[0] + nt[1]) {
-      const TileCount k = push_tile<R, 1>(C, D, L, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
+      const TileCount k = push_tile<R, 1>(C, D, L, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
       ps += k.pushed; an0 += k.abs0; an1 += k.abs1;
     } else {
-      const TileCount k = push_tile<R, 2>(C, D, L, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
+      const TileCount k = push_tile<R, 2>(C, D, L, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
       ps += k.pushed; ap0 += k.abs0; ap1 += k.abs1;
     }
   }
@@ -1179,8 +1271,8 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
     const R Erel = C.hmu_c[1] * g2;
     const uint4 w = rng(C, q.id, n, 2);
     R n1[3], n2[3];
-    iso_dir<R>(w.x, w.y, n1);
-    iso_dir<R>(w.z, w.w, n2);
+    iso_dir<R>(C, w.x, w.y, n1);
+    iso_dir<R>(C, w.z, w.w, n2);
     const R Ep = Erel - C.loss[13];
     const R gp = Sqrt(Ep * C.c2e_c[1]);
     const R ag = a * gp, bg = b * gp;
@@ -1646,7 +1738,6 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
 // ---------------------------------------------------------------------------
 constexpr int COUL_TPB = 1024;
 constexpr int COUL_MAXC = 16384;                 // particles of one species in one cell
-constexpr int COUL_NB = COUL_MAXC / 4;           // buckets of the pairing order
 
 // one collision of two equal-mass particles; cc = prefactor times the cell count
 template <class R>
@@ -1665,7 +1756,7 @@ __device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R 
     st = Sqrt((R)1 - ct * ct);
     omc = (R)1 - ct;
   } else {
-    const R nrm = bm_radius<R>(unif<R>(w.x)) * cos2pi<R>(unif<R>(w.y));
+    const R nrm = bm_radius<R>(C, unif<R>(w.x)) * cos2pi<R>(C, unif<R>(w.y));
     const R d = Sqrt(var) * nrm;
     const R d2 = d * d;
     const R den = (R)1 + d2;
@@ -1673,7 +1764,7 @@ __device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R 
     omc = (d2 + d2) / den;
   }
   const R ph = unif<R>(w.z);
-  const R s1 = st * cos2pi<R>(ph), s2 = st * sin2pi<R>(ph);
+  const R s1 = st * cos2pi<R>(C, ph), s2 = st * sin2pi<R>(C, ph);
   R du[3];
   if (up2 > (R)0) {
     const R up = Sqrt(up2);
@@ -1728,113 +1819,241 @@ __device__ inline void block_scan_excl(int32_t* a, int n, int32_t* wsum) {
   __syncthreads();
 }
 
-struct CoulLds {
-  uint32_t h[COUL_MAXC];     // pairing hash by segment position
-  uint16_t list[COUL_MAXC];  // positions grouped by bucket
-  uint16_t ord[COUL_MAXC];   // positions in pairing order
-  int32_t bend[COUL_NB];     // bucket starts, then bucket ends
-  int32_t wsum[COUL_TPB / 64];
-};
-
 __device__ __forceinline__ int coul_bucket(uint32_t h, int nb) { return (int)(((uint64_t)h * (uint32_t)nb) >> 32); }
 
-// One workgroup per (species, cell) segment at a time.  The pairing order is
-// the particles sorted by (Philox(id, n, 16).x, id): a counting sort into
-// nb = ceil(m/4) buckets on the hash (monotone in it), then each particle's
-// rank is its bucket start plus the members of its bucket that precede it.
+// Pairing order of the Coulomb pass: the particles of one (species, cell)
+// segment ordered by (Philox(id, n, 16).x, id).  A counting sort into
+// nb = ceil(m/per) LDS buckets on the hash (monotone in it); a particle's rank
+// is its bucket start plus the members of its bucket that precede it.
+// Returns through ordp[r] (or ordg[a + r]) the position of the particle of rank r.
 template <class R>
-__global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
-  __shared__ CoulLds L;
-  const int N = C.N;
+__device__ void coul_rank(const Consts<R>& C, const Store<R>& S, int32_t a, int m, int per, uint32_t n, uint32_t* h,
+                          uint16_t* list, int32_t* bend, int32_t* wsum, uint16_t* ordp, int32_t* ordg) {
   const int tid = threadIdx.x;
-  for (int w = blockIdx.x; w < 3 * N; w += gridDim.x) {
-    const int s = w / N, cell = w - s * N;
-    const int32_t a = D.seg[s * (N + 1) + cell];
-    const int m = D.seg[s * (N + 1) + cell + 1] - a;
-    if (m < 2) continue;
-    if (m > COUL_MAXC) {
-      if (tid == 0) atomicOr(&D.ctr->err, ERR_COUL);
-      continue;
+  const int nb = (m + per - 1) / per;
+  for (int i = tid; i < nb; i += COUL_TPB) bend[i] = 0;
+  __syncthreads();
+  for (int i = tid; i < m; i += COUL_TPB) {
+    const uint32_t x = rng(C, S.id[a + i], n, 16).x;
+    h[i] = x;
+    atomicAdd(&bend[coul_bucket(x, nb)], 1);
+  }
+  __syncthreads();
+  block_scan_excl(bend, nb, wsum);
+  for (int i = tid; i < m; i += COUL_TPB) {
+    const int pos = atomicAdd(&bend[coul_bucket(h[i], nb)], 1);
+    list[pos] = (uint16_t)i;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += COUL_TPB) {
+    const uint32_t hi = h[i];
+    const int b = coul_bucket(hi, nb);
+    const int b0 = b > 0 ? bend[b - 1] : 0, b1 = bend[b];
+    int r = b0;
+    for (int k = b0; k < b1; k++) {
+      const int j = list[k];
+      const uint32_t hj = h[j];
+      if (hj < hi || (hj == hi && j != i && S.id[a + j] < S.id[a + i])) r++;
     }
-    const Store<R> S = D.st[s];
-    const int nb = (m + 3) >> 2;
-    for (int i = tid; i < nb; i += COUL_TPB) L.bend[i] = 0;
-    __syncthreads();
-    for (int i = tid; i < m; i += COUL_TPB) {
-      const uint32_t h = rng(C, S.id[a + i], n, 16).x;
-      L.h[i] = h;
-      atomicAdd(&L.bend[coul_bucket(h, nb)], 1);
-    }
-    __syncthreads();
-    block_scan_excl(L.bend, nb, L.wsum);
-    for (int i = tid; i < m; i += COUL_TPB) {
-      const int pos = atomicAdd(&L.bend[coul_bucket(L.h[i], nb)], 1);
-      L.list[pos] = (uint16_t)i;
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += COUL_TPB) {
-      const uint32_t hi = L.h[i];
-      const int b = coul_bucket(hi, nb);
-      const int b0 = b > 0 ? L.bend[b - 1] : 0, b1 = L.bend[b];
-      int r = b0;
-      for (int k = b0; k < b1; k++) {
-        const int j = L.list[k];
-        const uint32_t hj = L.h[j];
-        if (hj < hi || (hj == hi && j != i && S.id[a + j] < S.id[a + i])) r++;
-      }
-      L.ord[r] = (uint16_t)i;
-    }
-    __syncthreads();
-    // pairs (o[q], o[q+1]); an odd cell first runs the triangle (o0,o1), (o1,o2),
-    // (o2,o0) with half the interval, in that order, on one thread
-    const int first = (m & 1) ? 3 : 0;
-    const int npairs = (m - first) >> 1;
-    const R cf = C.ccoul[s] * (R)m;
-    for (int p = tid; p < npairs + (first ? 1 : 0); p += COUL_TPB) {
-      if (first && p == npairs) {
-        const R ch = C.ccoul_h[s] * (R)m;
-        if (L.ord[0] >= m || L.ord[1] >= m || L.ord[2] >= m) {
-          atomicOr(&D.ctr->err, ERR_COUL);
-          continue;
-        }
-        const int i0 = a + L.ord[0], i1 = a + L.ord[1], i2 = a + L.ord[2];
-        R v0[3], v1[3], v2[3];
-        v0[0] = S.vx[i0];
-        ld_yz(S, i0, v0[1], v0[2]);
-        v1[0] = S.vx[i1];
-        ld_yz(S, i1, v1[1], v1[2]);
-        v2[0] = S.vx[i2];
-        ld_yz(S, i2, v2[1], v2[2]);
-        ta_pair<R>(C, v0, v1, ch, S.id[i0], n, 17);
-        ta_pair<R>(C, v1, v2, ch, S.id[i1], n, 18);
-        ta_pair<R>(C, v2, v0, ch, S.id[i2], n, 19);
-        S.vx[i0] = v0[0];
-        st_yz(S, i0, v0[1], v0[2]);
-        S.vx[i1] = v1[0];
-        st_yz(S, i1, v1[1], v1[2]);
-        S.vx[i2] = v2[0];
-        st_yz(S, i2, v2[1], v2[2]);
-        continue;
-      }
-      const int q = first + 2 * p;
-      if (L.ord[q] >= m || L.ord[q + 1] >= m) {  // not a permutation: ids were not unique
+    if (ordp) ordp[r] = (uint16_t)i;
+    else ordg[a + r] = a + i;
+  }
+  __syncthreads();
+}
+
+// Collisions of a cell whose velocities are in (vx, vy, vz)[0..m) (LDS or
+// global, indexed by segment position through ord); one thread per pair, an
+// odd cell first runs the triangle (o0,o1), (o1,o2), (o2,o0) with half the
+// interval, in that order, on one thread.  The random numbers of the collision
+// whose first particle has rank q are keyed by ((s N + cell) 2^32 + q).
+template <class R, class ORD, class VX, class VYZ>
+__device__ __forceinline__ void coul_pairs(const Consts<R>& C, const Dev<R>& D, int s, int cell, int m, uint32_t n,
+                                           ORD ord, VX vx, VYZ vyz, int tpb) {
+  const uint64_t key = (uint64_t)(s * C.N + cell) << 32;
+  const int first = (m & 1) ? 3 : 0;
+  const int npairs = (m - first) >> 1;
+  const R cf = C.ccoul[s] * (R)m;
+  for (int p = threadIdx.x; p < npairs + (first ? 1 : 0); p += tpb) {
+    if (first && p == npairs) {
+      const R ch = C.ccoul_h[s] * (R)m;
+      const int i0 = ord(0), i1 = ord(1), i2 = ord(2);
+      if (i0 >= m || i1 >= m || i2 >= m) {
         atomicOr(&D.ctr->err, ERR_COUL);
         continue;
       }
-      const int ia = a + L.ord[q], ib = a + L.ord[q + 1];
-      R va[3], vb[3];
-      va[0] = S.vx[ia];
-      ld_yz(S, ia, va[1], va[2]);
-      vb[0] = S.vx[ib];
-      ld_yz(S, ib, vb[1], vb[2]);
-      ta_pair<R>(C, va, vb, cf, S.id[ia], n, 17);
-      S.vx[ia] = va[0];
-      st_yz(S, ia, va[1], va[2]);
-      S.vx[ib] = vb[0];
-      st_yz(S, ib, vb[1], vb[2]);
+      R v0[3], v1[3], v2[3];
+      v0[0] = vx(i0);
+      vyz.get(i0, v0[1], v0[2]);
+      v1[0] = vx(i1);
+      vyz.get(i1, v1[1], v1[2]);
+      v2[0] = vx(i2);
+      vyz.get(i2, v2[1], v2[2]);
+      ta_pair<R>(C, v0, v1, ch, key | 0u, n, 17);
+      ta_pair<R>(C, v1, v2, ch, key | 1u, n, 18);
+      ta_pair<R>(C, v2, v0, ch, key | 2u, n, 19);
+      vx(i0) = v0[0];
+      vyz.set(i0, v0[1], v0[2]);
+      vx(i1) = v1[0];
+      vyz.set(i1, v1[1], v1[2]);
+      vx(i2) = v2[0];
+      vyz.set(i2, v2[1], v2[2]);
+      continue;
     }
+    const int q = first + 2 * p;
+    const int ia = ord(q), ib = ord(q + 1);
+    if (ia >= m || ib >= m) {  // not a permutation: ids were not unique
+      atomicOr(&D.ctr->err, ERR_COUL);
+      continue;
+    }
+    R va[3], vb[3];
+    va[0] = vx(ia);
+    vyz.get(ia, va[1], va[2]);
+    vb[0] = vx(ib);
+    vyz.get(ib, vb[1], vb[2]);
+    ta_pair<R>(C, va, vb, cf, key | (uint64_t)q, n, 17);
+    vx(ia) = va[0];
+    vyz.set(ia, va[1], va[2]);
+    vx(ib) = vb[0];
+    vyz.set(ib, vb[1], vb[2]);
+  }
+}
+
+template <class R>
+struct LdsVyz {
+  R* y;
+  R* z;
+  __device__ void get(int i, R& a, R& b) const { a = y[i]; b = z[i]; }
+  __device__ void set(int i, R a, R b) const { y[i] = a; z[i] = b; }
+};
+template <class R>
+struct GlobVyz {
+  Store<R> S;
+  int32_t a;
+  __device__ void get(int i, R& y, R& z) const { ld_yz(S, a + i, y, z); }
+  __device__ void set(int i, R y, R z) const { st_yz(S, a + i, y, z); }
+};
+
+// Coulomb pass, cells of at most CoulCap<R>::M particles: one workgroup per
+// (species, cell).  The pairing order is built in LDS, then the cell's
+// velocities are staged in LDS (reusing the sort's arrays), collided there and
+// written back, so that every global access is coalesced.  Larger cells are
+// listed for k_coul_order / k_coul_big.
+template <class R> struct CoulCap;
+template <> struct CoulCap<float> { static constexpr int M = 8192; };
+template <> struct CoulCap<double> { static constexpr int M = 4096; };
+
+template <class R>
+struct CoulLds {
+  static constexpr int M = CoulCap<R>::M;
+  union {
+    struct {
+      uint32_t h[M];
+      uint16_t list[M];
+      int32_t bend[M];
+    } o;
+    struct {
+      R vx[M], vy[M], vz[M];
+    } v;
+  } u;
+  uint16_t ord[M];
+  int32_t wsum[COUL_TPB / 64];
+};
+
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
+  __shared__ CoulLds<R> L;
+  constexpr int M = CoulCap<R>::M;
+  const int N = C.N;
+  const int tid = threadIdx.x;
+  const int w = blockIdx.x;
+  const int s = w / N, cell = w - s * N;
+  const int32_t a = D.seg[s * (N + 1) + cell];
+  const int m = D.seg[s * (N + 1) + cell + 1] - a;
+  if (m < 2) return;
+  if (m > M) {
+    if (tid == 0) {
+      const int k = atomicAdd(D.ncoul, 1);
+      if (k < 3 * N) D.coul_big[k] = w;
+    }
+    return;
+  }
+  const Store<R> S = D.st[s];
+  // the velocities are loaded with the ids and parked in registers while the
+  // order is built in the LDS they will occupy
+  constexpr int PT = M / COUL_TPB;
+  R pvx[PT], pvy[PT], pvz[PT];
+#pragma unroll
+  for (int j = 0; j < PT; j++) {
+    const int i = tid + j * COUL_TPB;
+    pvx[j] = pvy[j] = pvz[j] = (R)0;
+    if (i < m) {
+      pvx[j] = S.vx[a + i];
+      ld_yz(S, a + i, pvy[j], pvz[j]);
+    }
+  }
+  coul_rank<R>(C, S, a, m, 1, n, L.u.o.h, L.u.o.list, L.u.o.bend, L.wsum, L.ord, nullptr);
+#pragma unroll
+  for (int j = 0; j < PT; j++) {
+    const int i = tid + j * COUL_TPB;
+    if (i < m) {
+      L.u.v.vx[i] = pvx[j];
+      L.u.v.vy[i] = pvy[j];
+      L.u.v.vz[i] = pvz[j];
+    }
+  }
+  __syncthreads();
+  R* vx = L.u.v.vx;
+  coul_pairs<R>(C, D, s, cell, m, n, [&](int r) -> int { return L.ord[r]; }, [&](int i) -> R& { return vx[i]; },
+                LdsVyz<R>{L.u.v.vy, L.u.v.vz}, COUL_TPB);
+  __syncthreads();
+  for (int i = tid; i < m; i += COUL_TPB) {
+    S.vx[a + i] = L.u.v.vx[i];
+    st_yz(S, a + i, L.u.v.vy[i], L.u.v.vz[i]);
+  }
+}
+
+// cells listed by k_coulomb (more than CoulCap<R>::M particles, at most
+// COUL_MAXC): the order goes to the cell array of the sort's other buffer and
+// the collisions read and write the store directly
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D, uint32_t n) {
+  __shared__ uint32_t h[COUL_MAXC];
+  __shared__ uint16_t list[COUL_MAXC];
+  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ int32_t wsum[COUL_TPB / 64];
+  const int N = C.N;
+  const int nunits = min(*D.ncoul, 3 * N);
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int w = D.coul_big[u];
+    const int s = w / N, cell = w - s * N;
+    const int32_t a = D.seg[s * (N + 1) + cell];
+    const int m = D.seg[s * (N + 1) + cell + 1] - a;
+    if (m > COUL_MAXC) {
+      if (threadIdx.x == 0) atomicOr(&D.ctr->err, ERR_COUL);
+      continue;
+    }
+    const Store<R> S = D.st[s];
+    int32_t* ordg = D.alt[s].cell;
+    coul_rank<R>(C, S, a, m, 4, n, h, list, bend, wsum, nullptr, ordg);
+    coul_pairs<R>(C, D, s, cell, m, n, [&](int r) -> int { return ordg[a + r] - a; },
+                  [&](int i) -> R& { return S.vx[a + i]; }, GlobVyz<R>{S, a}, COUL_TPB);
     __syncthreads();
   }
+}
+
+template <class R>
+__global__ void k_coul_reset(Consts<R> C, Dev<R> D) {
+  if (threadIdx.x == 0) *D.ncoul = 0;
+}
+
+// the Coulomb pass after a sort: reset of the big-cell list, cells that fit
+// in LDS, then the big cells on a persistent grid
+template <class R>
+inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, uint32_t n, int ncu, hipStream_t st) {
+  hipLaunchKernelGGL(k_coul_reset<R>, dim3(1), dim3(64), 0, st, C, D);
+  hipLaunchKernelGGL(k_coulomb<R>, dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+  hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D, n);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1861,10 +2080,10 @@ __global__ void k_load(Consts<R> C, Dev<R> D, int64_t n_e, int64_t n_n, int64_t 
   st.id[i] = (uint64_t)id;
   st.cell[i] = (int32_t)(((uint64_t)w.x * (uint64_t)C.N) >> 32);
   st.off[i] = unif<R>(w.y);
-  R r1 = bm_radius<R>(unif<R>(u.x)), a1 = unif<R>(u.y);
-  R r2 = bm_radius<R>(unif<R>(u.z)), a2 = unif<R>(u.w);
-  st.vx[i] = C.vth0[s] * (r1 * cos2pi<R>(a1));
-  st_yz(st, i, C.vth0[s] * (r1 * sin2pi<R>(a1)), C.vth0[s] * (r2 * cos2pi<R>(a2)));
+  R r1 = bm_radius<R>(C, unif<R>(u.x)), a1 = unif<R>(u.y);
+  R r2 = bm_radius<R>(C, unif<R>(u.z)), a2 = unif<R>(u.w);
+  st.vx[i] = C.vth0[s] * (r1 * cos2pi<R>(C, a1));
+  st_yz(st, i, C.vth0[s] * (r1 * sin2pi<R>(C, a1)), C.vth0[s] * (r2 * cos2pi<R>(C, a2)));
 }
 
 template <class R>

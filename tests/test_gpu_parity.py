@@ -207,6 +207,22 @@ def test_coulomb_dense_cells_match_oracle():
         compare(g, o, "fp32", f"dense coulomb step {2 * (k + 1)}")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_coulomb_big_cells_match_oracle(prec):
+    """About 10000 particles of a species per cell, more than the cells whose
+    velocities are staged in LDS (8192 in FP32, 4096 in FP64): these take the
+    path that orders in LDS and collides in global memory."""
+    wl = dataclasses.replace(workload("small"), n_cells=8, n_init=(80001, 1001, 79999), sort_every=2,
+                             coulomb_every=2)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    for k in range(2):
+        g.step(2)
+        o.step(2)
+        compare(g, o, prec, f"big-cell coulomb step {2 * (k + 1)}")
+
+
 def test_coulomb_cell_overflow_is_reported():
     """More than 16384 particles of one species in a cell: the Coulomb pass
     reports PIC_EOVERFLOW instead of pairing a part of the cell."""

@@ -428,3 +428,29 @@ def test_fp32_and_fp64_agree_statistically():
         assert res[0][0][s] == pytest.approx(res[1][0][s], rel=0.03)
     q32, q64 = res[0][1].astype(float), res[1][1].astype(float)
     assert np.abs(q32 - q64).sum() / q64.sum() < 0.05
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sampler_elementary_functions_against_numpy(prec):
+    """sin/cos(2 pi u) and ln(u) of the samplers (series with fixed term
+    counts) against numpy in double, on the uniforms the generator produces
+    and on the quadrant edges."""
+    rng = np.random.default_rng(7)
+    w = rng.integers(0, 2**32, 200000, dtype=np.uint64)
+    if prec == "fp32":
+        u = ((w >> 9).astype(np.float64) + 0.5) * 2.0**-23
+        edges = np.array([0.5, 1, 2, 1023, 1024, 2047, 2048, 4095, 4096, 6143, 6144, 8191]) * 2.0**-13
+        u = np.concatenate([u, edges, [2.0**-24, 1 - 2.0**-24]])
+        tol_trig, tol_log = 3e-7, 3e-7
+    else:
+        u = (w.astype(np.float64) + 0.5) * 2.0**-32
+        u = np.concatenate([u, [0.125, 0.25, 0.375, 0.5, 0.625, 0.75, 0.875, 2.0**-33, 1 - 2.0**-33]])
+        # numpy's own argument 2*pi*u is rounded: about 4 ulp of 2 pi
+        tol_trig, tol_log = 1.5e-15, 6e-16
+    sn, cs, lg = O.math(u, prec)
+    assert np.max(np.abs(sn - np.sin(2 * np.pi * u))) < tol_trig
+    assert np.max(np.abs(cs - np.cos(2 * np.pi * u))) < tol_trig
+    assert np.max(np.abs(lg - np.log(u)) / np.maximum(1.0, np.abs(np.log(u)))) < tol_log
+    # exact values where the quadrant reduction lands on a node
+    s0, c0, l1 = O.math(np.array([0.25, 0.5, 0.75]), prec)
+    assert np.allclose(s0, [1, 0, -1], atol=tol_trig) and np.allclose(c0, [0, -1, 0], atol=tol_trig)
