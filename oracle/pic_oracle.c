@@ -994,18 +994,19 @@ static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint3
     real nrm = bm_radius(unif(w[0])) * cos2pi(unif(w[1]));
     real d = RSQRT(var) * nrm;
     real d2 = d * d;
-    real den = (real)1 + d2;
-    st = (d + d) / den;
-    omc = (d2 + d2) / den;
+    real inv = (real)1 / ((real)1 + d2);
+    st = (d + d) * inv;
+    omc = (d2 + d2) * inv;
   }
   real ph = unif(w[2]);
   real s1 = st * cos2pi(ph), s2 = st * sin2pi(ph);
   real du[3];
   if (up2 > (real)0) {
     real up = RSQRT(up2);
+    real iup = (real)1 / up;
     real r = uz * s1, t = u * s2;
-    du[0] = (ux * r - uy * t) / up - ux * omc;
-    du[1] = (uy * r + ux * t) / up - uy * omc;
+    du[0] = (ux * r - uy * t) * iup - ux * omc;
+    du[1] = (uy * r + ux * t) * iup - uy * omc;
     du[2] = -(up * s1) - uz * omc;
   } else {
     du[0] = u * s1;

@@ -60,9 +60,10 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
-    L = C.CDLL(LIB_PATH)
+    path = os.environ.get("PIC_LIBRARY", LIB_PATH)  # another build of the same C ABI
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(path)
     P = C.POINTER
     L.pic_create.argtypes = [P(Geometry), P(Gas), C.c_double, C.c_double, C.c_double, P(C.c_void_p)]
     L.pic_set_stream.argtypes = [C.c_void_p, C.c_void_p]

@@ -1759,18 +1759,21 @@ __device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R 
     const R nrm = bm_radius<R>(C, unif<R>(w.x)) * cos2pi<R>(C, unif<R>(w.y));
     const R d = Sqrt(var) * nrm;
     const R d2 = d * d;
-    const R den = (R)1 + d2;
-    st = (d + d) / den;
-    omc = (d2 + d2) / den;
+    const R inv = (R)1 / ((R)1 + d2);
+    st = (d + d) * inv;
+    omc = (d2 + d2) * inv;
   }
   const R ph = unif<R>(w.z);
-  const R s1 = st * cos2pi<R>(C, ph), s2 = st * sin2pi<R>(C, ph);
+  R sph, cph;
+  sincos2pi<R>(C, ph, sph, cph);
+  const R s1 = st * cph, s2 = st * sph;
   R du[3];
   if (up2 > (R)0) {
     const R up = Sqrt(up2);
+    const R iup = (R)1 / up;
     const R r = uz * s1, t = u * s2;
-    du[0] = (ux * r - uy * t) / up - ux * omc;
-    du[1] = (uy * r + ux * t) / up - uy * omc;
+    du[0] = (ux * r - uy * t) * iup - ux * omc;
+    du[1] = (uy * r + ux * t) * iup - uy * omc;
     du[2] = -(up * s1) - uz * omc;
   } else {
     du[0] = u * s1;
@@ -1918,6 +1921,91 @@ __device__ __forceinline__ void coul_pairs(const Consts<R>& C, const Dev<R>& D, 
   }
 }
 
+// exclusive prefix sum of a[0..n) in LDS by one COUL_TPB workgroup: each
+// wave scans a contiguous chunk with consecutive lanes on consecutive
+// elements (no bank conflicts), then the wave totals are added
+__device__ inline void block_scan_chunked(int32_t* a, int n, int32_t* wsum) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = COUL_TPB / 64;
+  const int chunk = ((n + NW * 64 - 1) / (NW * 64)) * 64;
+  const int base = wv * chunk;
+  int run = 0;
+  for (int j = 0; j < chunk; j += 64) {
+    const int i = base + j + lane;
+    const int x = i < n ? a[i] : 0;
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    if (i < n) a[i] = run + incl - x;
+    run += __shfl(incl, 63);
+  }
+  if (lane == 0) wsum[wv] = run;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wv; w++) off += wsum[w];
+  if (off)
+    for (int j = 0; j < chunk; j += 64) {
+      const int i = base + j + lane;
+      if (i < n) a[i] += off;
+    }
+  __syncthreads();
+}
+
+// The pairing order of a cell that fits in LDS: one bucket per particle on
+// average (nb = m); a thread keeps the hashes of its PT positions in
+// registers; bucket members are (hash << 16 | position) entries, so that the
+// rank of a particle reads one LDS word per member.
+template <class R, int PT>
+__device__ void coul_rank_lds(const Consts<R>& C, const Store<R>& S, int32_t a, int m, uint32_t n, uint64_t* list,
+                              int32_t* bend, int32_t* wsum, uint16_t* ord) {
+  const int tid = threadIdx.x;
+  const int nb = m;
+  for (int i = tid; i < nb; i += COUL_TPB) bend[i] = 0;
+  __syncthreads();
+  uint32_t hr[PT];
+#pragma unroll
+  for (int j = 0; j < PT; j++) {
+    const int i = tid + j * COUL_TPB;
+    hr[j] = 0;
+    if (i < m) {
+      hr[j] = rng(C, S.id[a + i], n, 16).x;
+      atomicAdd(&bend[coul_bucket(hr[j], nb)], 1);
+    }
+  }
+  __syncthreads();
+  block_scan_chunked(bend, nb, wsum);
+#pragma unroll
+  for (int j = 0; j < PT; j++) {
+    const int i = tid + j * COUL_TPB;
+    if (i < m) {
+      const int pos = atomicAdd(&bend[coul_bucket(hr[j], nb)], 1);
+      list[pos] = ((uint64_t)hr[j] << 16) | (uint64_t)i;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PT; j++) {
+    const int i = tid + j * COUL_TPB;
+    if (i < m) {
+      const uint32_t hi = hr[j];
+      const int b = coul_bucket(hi, nb);
+      const int b0 = b > 0 ? bend[b - 1] : 0, b1 = bend[b];
+      int r = b0;
+      for (int k = b0; k < b1; k++) {
+        const uint64_t e = list[k];
+        const uint32_t hj = (uint32_t)(e >> 16);
+        const int pj = (int)(e & 0xFFFFu);
+        if (hj < hi || (hj == hi && pj != i && S.id[a + pj] < S.id[a + i])) r++;
+      }
+      ord[r] = (uint16_t)i;
+    }
+  }
+  __syncthreads();
+}
+
 template <class R>
 struct LdsVyz {
   R* y;
@@ -1947,8 +2035,7 @@ struct CoulLds {
   static constexpr int M = CoulCap<R>::M;
   union {
     struct {
-      uint32_t h[M];
-      uint16_t list[M];
+      uint64_t list[M];  // (hash << 16 | position), grouped by bucket
       int32_t bend[M];
     } o;
     struct {
@@ -1991,7 +2078,7 @@ __global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uin
       ld_yz(S, a + i, pvy[j], pvz[j]);
     }
   }
-  coul_rank<R>(C, S, a, m, 1, n, L.u.o.h, L.u.o.list, L.u.o.bend, L.wsum, L.ord, nullptr);
+  coul_rank_lds<R, PT>(C, S, a, m, n, L.u.o.list, L.u.o.bend, L.wsum, L.ord);
 #pragma unroll
   for (int j = 0; j < PT; j++) {
     const int i = tid + j * COUL_TPB;
