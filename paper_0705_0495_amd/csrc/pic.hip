@@ -3,8 +3,8 @@
 // The host computes the constants of a discharge once (in double, rounded
 // once to the particle precision), owns the device memory and enqueues the
 // kernels of each step on one HIP stream:
-//   k_push     fused gather/push/absorb/null test/deposit (persistent grid)
-//   k_collide  collisions of the null-test candidates (persistent grid)
+//   k_push     fused gather/push/absorb/null test/deposit, then the
+//              collisions of each workgroup's candidates (persistent grid)
 //   k_serial   partner reactions, births, closing the step and the field
 //              solve of the next step (1 workgroup)
 //   k_sort_*   every sort_every steps, followed by k_coulomb (every
@@ -113,7 +113,7 @@ struct Impl : Base {
   Consts<R> C;
   Dev<R> D;
   std::vector<void*> allocs;
-  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, grid_collide = 0, ncu = 1;
+  int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, ncu = 1;
   int64_t nstep = 0;  // steps enqueued
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
@@ -332,7 +332,6 @@ struct Impl : Base {
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
     grid_scatter = std::max(1, ncu * 4);
-    grid_collide = std::max(1, ncu * 8);
 
 
     // initial load, deposit, field at t = 0, half step back, first sort
@@ -387,7 +386,6 @@ struct Impl : Base {
       }
       hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
-      hipLaunchKernelGGL(k_collide<R>, dim3(grid_collide), dim3(COLL_TPB), 0, c->stream, C, D);
       HIPCHK(c, hipGetLastError());
       nstep++;
       const bool sort_now = (nstep % sort_every) == 0;

@@ -820,64 +820,9 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
   diag_alive<R, S>(C, G, cell, v[0], v[1], v[2]);
 }
 
-constexpr int COLL_TPB = 256;
-constexpr int COLL_GROUP = 32;  // candidate regions (one per push wave) per workgroup iteration
-
-template <class R, int S>
-__device__ __forceinline__ void collide_group(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int32_t* pre,
-                                              int64_t reg0, int64_t nreg, uint32_t n) {
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    // inclusive scan of the group's candidate counts in the first wave
-    int x = (tid < COLL_GROUP && reg0 + tid < nreg) ? D.tcnt[S][reg0 + tid] : 0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d);
-      if (tid >= d) x += y;
-    }
-    if (tid < COLL_GROUP) pre[tid + 1] = x;
-    if (tid == 0) pre[0] = 0;
-  }
-  __syncthreads();
-  const int tot = pre[COLL_GROUP];
-  for (int e = tid; e < tot; e += COLL_TPB) {
-    int lo = 0, hi = COLL_GROUP;  // the region k with pre[k] <= e < pre[k+1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pre[mid] <= e) lo = mid;
-      else hi = mid;
-    }
-    collide_one<R, S>(C, D, G, (reg0 + lo) * WTILE + (e - pre[lo]), n);
-  }
-  __syncthreads();
-}
-
-template <class R>
-__global__ void __launch_bounds__(COLL_TPB) k_collide(Consts<R> C, Dev<R> D) {
-  __shared__ DiagLds G;
-  __shared__ int32_t pre[COLL_GROUP + 1];
-  diag_init(G);
-  __syncthreads();
-  const int64_t nstep = D.ctr->step;
-  const uint32_t n = (uint32_t)nstep;
-  const bool ion = (nstep % C.nsub) == 0;
-  int64_t nt[3], ng[3];
-  for (int s = 0; s < 3; s++) {
-    const int64_t Ns = (s == 0 || ion) ? D.N[s] : 0;
-    nt[s] = (Ns + WTILE - 1) / WTILE;
-    ng[s] = (nt[s] + COLL_GROUP - 1) / COLL_GROUP;
-  }
-  const int64_t total = ng[0] + ng[1] + ng[2];
-  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-    if (g < ng[0]) collide_group<R, 0>(C, D, G, pre, g * COLL_GROUP, nt[0], n);
-    else if (g < ng[0] + ng[1]) collide_group<R, 1>(C, D, G, pre, (g - ng[0]) * COLL_GROUP, nt[1], n);
-    else collide_group<R, 2>(C, D, G, pre, (g - ng[0] - ng[1]) * COLL_GROUP, nt[2], n);
-  }
-  diag_flush(C, D, G);
-}
-
 // ---------------------------------------------------------------------------
-// fused push: gather, leapfrog, absorption, null-collision test, deposit
+// fused particle step: gather, leapfrog, absorption, null-collision test,
+// deposit; then the collisions of the workgroup's own candidates
 // ---------------------------------------------------------------------------
 template <class R>
 struct PushLds {
@@ -1137,7 +1082,52 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   if (an1) atomicAdd(&L.G.absorbed[4], an1);
   if (ap1) atomicAdd(&L.G.absorbed[5], ap1);
   if (ps) atomicAdd(&L.G.psteps, ps);
+  // collisions of this workgroup's own candidates, in batches of up to FB
+  // tiles of one species
   __syncthreads();
+  {
+    constexpr int FB = 16;
+    __shared__ int32_t cpre[FB * 4 + 1];
+    int64_t t = blockIdx.x;
+    while (t < total) {
+      const int s = t < nt[0] ? 0 : (t < nt[0] + nt[1] ? 1 : 2);
+      const int64_t tb = s == 0 ? 0 : (s == 1 ? nt[0] : nt[0] + nt[1]);
+      const int64_t tend = tb + nt[s];
+      int nbt = 0;
+      for (int64_t u = t; nbt < FB && u < tend; u += gridDim.x) nbt++;
+      if (tid < 64) {
+        int x = 0;
+        if (tid < nbt * 4) {
+          const int64_t tile = t + (int64_t)(tid >> 2) * gridDim.x - tb;
+          x = D.tcnt[s][tile * 4 + (tid & 3)];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(x, d);
+          if (tid >= d) x += y;
+        }
+        if (tid < FB * 4) cpre[tid + 1] = x;
+        if (tid == 0) cpre[0] = 0;
+      }
+      __syncthreads();
+      const int tot = cpre[nbt * 4];
+      for (int e = tid; e < tot; e += TPB) {
+        int lo = 0, hi = nbt * 4;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (cpre[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        const int64_t tile = t + (int64_t)(lo >> 2) * gridDim.x - tb;
+        const int64_t r = tile * TILE + (lo & 3) * WTILE + (e - cpre[lo]);
+        if (s == 0) collide_one<R, 0>(C, D, L.G, r, n);
+        else if (s == 1) collide_one<R, 1>(C, D, L.G, r, n);
+        else collide_one<R, 2>(C, D, L.G, r, n);
+      }
+      __syncthreads();
+      t += (int64_t)nbt * gridDim.x;
+    }
+  }
   diag_flush(C, D, L.G);
 }
 
