@@ -913,7 +913,15 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   }
   bool was_dead[PPT];
 #pragma unroll
-  for (int q = 0; q < PPT; q++) was_dead[q] = c[q] == DEAD;
+  for (int q = 0; q < PPT; q++) {
+    // a cell outside the grid can only come from a corrupted store: report it
+    // and leave the slot alone rather than read past the field arrays
+    if (c[q] != DEAD && (unsigned)c[q] >= (unsigned)N) {
+      atomicOr(&D.ctr->err, ERR_NAN);
+      c[q] = DEAD;
+    }
+    was_dead[q] = c[q] == DEAD;
+  }
   int candmask = 0;
   // a thread's consecutive particles mostly share a cell: one atomic per run
   int run_cell = -1;
@@ -1528,15 +1536,19 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
     pmax[tid] = max(pmax[tid], y);
     __syncthreads();
   }
+  // segments never reach past the store's capacity, whatever the counts say
+  const int64_t cap = D.cap[s];
   int64_t run = part[tid] - sum;
   for (int i = i0; i < i1; i++) {
-    D.seg[s * (N + 1) + i] = (int32_t)run;
-    D.cursor[s * N + i] = (int32_t)run;
+    D.seg[s * (N + 1) + i] = (int32_t)min(run, cap);
+    D.cursor[s * N + i] = (int32_t)min(run, cap);
     run += D.cnt[s * N + i];
   }
   if (tid == SCAN_TPB - 1) {
-    D.seg[s * (N + 1) + N] = (int32_t)part[SCAN_TPB - 1];
-    D.Nnew[s] = part[SCAN_TPB - 1];
+    const int64_t total = part[SCAN_TPB - 1];
+    if (total > cap) atomicOr(&D.ctr->err, ERR_SORT);
+    D.seg[s * (N + 1) + N] = (int32_t)min(total, cap);
+    D.Nnew[s] = min(total, cap);
     D.segmax[s] = pmax[SCAN_TPB - 1];
   }
 }
@@ -1685,7 +1697,7 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
         L.id[p] = id[j];
       } else {
         const int32_t dst = rank[j] & ~(1 << 30);
-        if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1]) {
+        if (dst < seg[cell[j]] || dst >= seg[cell[j] + 1] || dst >= D.cap[s]) {
           atomicOr(&D.ctr->err, ERR_SORT);
           continue;
         }
@@ -1702,7 +1714,7 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
       const int32_t cl = L.cell[k];
       const int idx = cl - base;
       const int32_t dst = L.gb[idx] + (k - L.lst[idx]);
-      if (dst < seg[cl] || dst >= seg[cl + 1]) {
+      if (dst < seg[cl] || dst >= seg[cl + 1] || dst >= D.cap[s]) {
         atomicOr(&D.ctr->err, ERR_SORT);
         continue;
       }
