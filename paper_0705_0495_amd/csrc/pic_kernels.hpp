@@ -1923,12 +1923,13 @@ __device__ __forceinline__ void coul_pairs(const Consts<R>& C, const Dev<R>& D, 
   }
 }
 
-// exclusive prefix sum of a[0..n) in LDS by one COUL_TPB workgroup: each
-// wave scans a contiguous chunk with consecutive lanes on consecutive
+// exclusive prefix sum of a[0..n) in LDS by one workgroup of TPB threads:
+// each wave scans a contiguous chunk with consecutive lanes on consecutive
 // elements (no bank conflicts), then the wave totals are added
+template <int TPB>
 __device__ inline void block_scan_chunked(int32_t* a, int n, int32_t* wsum) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int NW = COUL_TPB / 64;
+  constexpr int NW = TPB / 64;
   const int chunk = ((n + NW * 64 - 1) / (NW * 64)) * 64;
   const int base = wv * chunk;
   int run = 0;
@@ -1960,17 +1961,17 @@ __device__ inline void block_scan_chunked(int32_t* a, int n, int32_t* wsum) {
 // average (nb = m); a thread keeps the hashes of its PT positions in
 // registers; bucket members are (hash << 16 | position) entries, so that the
 // rank of a particle reads one LDS word per member.
-template <class R, int PT>
+template <class R, int PT, int TPB>
 __device__ void coul_rank_lds(const Consts<R>& C, const Store<R>& S, int32_t a, int m, uint32_t n, uint64_t* list,
                               int32_t* bend, int32_t* wsum, uint16_t* ord) {
   const int tid = threadIdx.x;
   const int nb = m;
-  for (int i = tid; i < nb; i += COUL_TPB) bend[i] = 0;
+  for (int i = tid; i < nb; i += TPB) bend[i] = 0;
   __syncthreads();
   uint32_t hr[PT];
 #pragma unroll
   for (int j = 0; j < PT; j++) {
-    const int i = tid + j * COUL_TPB;
+    const int i = tid + j * TPB;
     hr[j] = 0;
     if (i < m) {
       hr[j] = rng(C, S.id[a + i], n, 16).x;
@@ -1978,10 +1979,10 @@ __device__ void coul_rank_lds(const Consts<R>& C, const Store<R>& S, int32_t a, 
     }
   }
   __syncthreads();
-  block_scan_chunked(bend, nb, wsum);
+  block_scan_chunked<TPB>(bend, nb, wsum);
 #pragma unroll
   for (int j = 0; j < PT; j++) {
-    const int i = tid + j * COUL_TPB;
+    const int i = tid + j * TPB;
     if (i < m) {
       const int pos = atomicAdd(&bend[coul_bucket(hr[j], nb)], 1);
       list[pos] = ((uint64_t)hr[j] << 16) | (uint64_t)i;
@@ -1990,7 +1991,7 @@ __device__ void coul_rank_lds(const Consts<R>& C, const Store<R>& S, int32_t a, 
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < PT; j++) {
-    const int i = tid + j * COUL_TPB;
+    const int i = tid + j * TPB;
     if (i < m) {
       const uint32_t hi = hr[j];
       const int b = coul_bucket(hi, nb);
@@ -2023,18 +2024,23 @@ struct GlobVyz {
   __device__ void set(int i, R y, R z) const { st_yz(S, a + i, y, z); }
 };
 
-// Coulomb pass, cells of at most CoulCap<R>::M particles: one workgroup per
-// (species, cell).  The pairing order is built in LDS, then the cell's
-// velocities are staged in LDS (reusing the sort's arrays), collided there and
-// written back, so that every global access is coalesced.  Larger cells are
-// listed for k_coul_order / k_coul_big.
+// Coulomb pass of the cells that fit in LDS: one workgroup per (species,
+// cell).  The pairing order is built in LDS, then the cell's velocities are
+// staged in LDS (reusing the sort's arrays), collided there and written back,
+// so that every global access is coalesced.  Size classes: up to 2048
+// particles in a 256-thread workgroup (several per CU), up to 5120 in a
+// 512-thread workgroup (FP32: two per CU), up to CoulCap<R>::M in a
+// 1024-thread workgroup; larger cells are listed for k_coul_big.
 template <class R> struct CoulCap;
 template <> struct CoulCap<float> { static constexpr int M = 8192; };
 template <> struct CoulCap<double> { static constexpr int M = 4096; };
+constexpr int COUL_SMALL = 2048;
+constexpr int COUL_STPB = 256;
+constexpr int COUL_MID = 5120;   // two workgroups per CU in FP32
+constexpr int COUL_MTPB = 512;
 
-template <class R>
+template <class R, int M, int TPB>
 struct CoulLds {
-  static constexpr int M = CoulCap<R>::M;
   union {
     struct {
       uint64_t list[M];  // (hash << 16 | position), grouped by bucket
@@ -2045,22 +2051,22 @@ struct CoulLds {
     } v;
   } u;
   uint16_t ord[M];
-  int32_t wsum[COUL_TPB / 64];
+  int32_t wsum[TPB / 64];
 };
 
-template <class R>
-__global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
-  __shared__ CoulLds<R> L;
-  constexpr int M = CoulCap<R>::M;
+// cells with MLO < m <= M; LIST: cells above M go to the big-cell list
+template <class R, int M, int TPB, int MLO, bool LIST>
+__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
+  __shared__ CoulLds<R, M, TPB> L;
   const int N = C.N;
   const int tid = threadIdx.x;
   const int w = blockIdx.x;
   const int s = w / N, cell = w - s * N;
   const int32_t a = D.seg[s * (N + 1) + cell];
   const int m = D.seg[s * (N + 1) + cell + 1] - a;
-  if (m < 2) return;
+  if (m < 2 || m <= MLO) return;
   if (m > M) {
-    if (tid == 0) {
+    if (LIST && tid == 0) {
       const int k = atomicAdd(D.ncoul, 1);
       if (k < 3 * N) D.coul_big[k] = w;
     }
@@ -2069,21 +2075,21 @@ __global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uin
   const Store<R> S = D.st[s];
   // the velocities are loaded with the ids and parked in registers while the
   // order is built in the LDS they will occupy
-  constexpr int PT = M / COUL_TPB;
+  constexpr int PT = M / TPB;
   R pvx[PT], pvy[PT], pvz[PT];
 #pragma unroll
   for (int j = 0; j < PT; j++) {
-    const int i = tid + j * COUL_TPB;
+    const int i = tid + j * TPB;
     pvx[j] = pvy[j] = pvz[j] = (R)0;
     if (i < m) {
       pvx[j] = S.vx[a + i];
       ld_yz(S, a + i, pvy[j], pvz[j]);
     }
   }
-  coul_rank_lds<R, PT>(C, S, a, m, n, L.u.o.list, L.u.o.bend, L.wsum, L.ord);
+  coul_rank_lds<R, PT, TPB>(C, S, a, m, n, L.u.o.list, L.u.o.bend, L.wsum, L.ord);
 #pragma unroll
   for (int j = 0; j < PT; j++) {
-    const int i = tid + j * COUL_TPB;
+    const int i = tid + j * TPB;
     if (i < m) {
       L.u.v.vx[i] = pvx[j];
       L.u.v.vy[i] = pvy[j];
@@ -2093,9 +2099,9 @@ __global__ void __launch_bounds__(COUL_TPB) k_coulomb(Consts<R> C, Dev<R> D, uin
   __syncthreads();
   R* vx = L.u.v.vx;
   coul_pairs<R>(C, D, s, cell, m, n, [&](int r) -> int { return L.ord[r]; }, [&](int i) -> R& { return vx[i]; },
-                LdsVyz<R>{L.u.v.vy, L.u.v.vz}, COUL_TPB);
+                LdsVyz<R>{L.u.v.vy, L.u.v.vz}, TPB);
   __syncthreads();
-  for (int i = tid; i < m; i += COUL_TPB) {
+  for (int i = tid; i < m; i += TPB) {
     S.vx[a + i] = L.u.v.vx[i];
     st_yz(S, a + i, L.u.v.vy[i], L.u.v.vz[i]);
   }
@@ -2139,8 +2145,16 @@ __global__ void k_coul_reset(Consts<R> C, Dev<R> D) {
 // in LDS, then the big cells on a persistent grid
 template <class R>
 inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, uint32_t n, int ncu, hipStream_t st) {
+  constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset<R>, dim3(1), dim3(64), 0, st, C, D);
-  hipLaunchKernelGGL(k_coulomb<R>, dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+  hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D, n);
+  if constexpr (MB > COUL_MID) {
+    hipLaunchKernelGGL((k_coulomb<R, COUL_MID, COUL_MTPB, COUL_SMALL, false>), dim3(3 * C.N), dim3(COUL_MTPB), 0, st,
+                       C, D, n);
+    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_MID, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+  } else {
+    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+  }
   hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D, n);
   return hipGetLastError();
 }
