@@ -115,6 +115,7 @@ struct Impl : Base {
   std::vector<void*> allocs;
   int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, ncu = 1;
   int64_t nstep = 0;  // steps enqueued
+  bool elds = false;  // k_push stages the node field in LDS
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
   ~Impl() override {
@@ -329,7 +330,9 @@ struct Impl : Base {
     int dev = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<R>, TPB, 0));
+    elds = N <= PushE<R>::MAXN;
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &occ, elds ? (const void*)k_push<R, true> : (const void*)k_push<R, false>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
     grid_scatter = std::max(1, ncu * 4);
 
@@ -384,7 +387,8 @@ struct Impl : Base {
         c->ev_used++;
         HIPCHK(c, hipEventRecord(e0, c->stream));
       }
-      hipLaunchKernelGGL(k_push<R>, dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
+      if (elds) hipLaunchKernelGGL((k_push<R, true>), dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
+      else hipLaunchKernelGGL((k_push<R, false>), dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
       HIPCHK(c, hipGetLastError());
       nstep++;

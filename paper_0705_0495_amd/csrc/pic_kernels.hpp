@@ -830,6 +830,12 @@ struct PushLds {
   DiagLds G;
 };
 
+// node field staged in LDS by k_push when the grid is small enough (16 KB)
+constexpr int PUSH_ELDS_BYTES = 16 * 1024 + 16;
+template <class R> struct PushE {
+  static constexpr int MAXN = PUSH_ELDS_BYTES / (int)sizeof(R) - 1;  // cells
+};
+
 template <class R> struct Vec4;
 template <> struct Vec4<float> {
   static __device__ __forceinline__ void load(const float* p, float o[4]) {
@@ -873,9 +879,10 @@ struct TileCount {
 // barrier; consecutive tiles alternate between two windows, so the next tile
 // starts while this one is flushed.  Each wave writes its candidates to its
 // own region of the list.
-template <class R, int S>
-__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, int buf,
-                                               int64_t t0, int64_t Ns, uint32_t n, uint64_t T0, double pmax) {
+template <class R, int S, bool ELDS>
+__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, const R* El,
+                                               int buf, int64_t t0, int64_t Ns, uint32_t n, uint64_t T0,
+                                               double pmax) {
   TileCount tc = {0, 0, 0};
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -930,7 +937,14 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   for (int q = 0; q < PPT; q++) {
     if (was_dead[q]) continue;
     tc.pushed++;
-    const R E0 = D.E2[2 * c[q]], E1 = D.E2[2 * c[q] + 1];
+    R E0, E1;
+    if (ELDS) {
+      E0 = El[c[q]];
+      E1 = El[c[q] + 1];
+    } else {
+      E0 = D.E2[2 * c[q]];
+      E1 = D.E2[2 * c[q] + 1];
+    }
     const R dE = E1 - E0;
     const R tt = off[q] * dE;
     const R Ep = E0 + tt;
@@ -1046,15 +1060,20 @@ __device__ __forceinline__ double pmax_of(const Consts<R>& C, const Dev<R>& D, i
   return P;
 }
 
-template <class R>
+// ELDS: the node field (rounded to R, the values of E2) is staged in LDS
+// and the gather reads it there; for grids up to PushE<R>::MAXN cells
+template <class R, bool ELDS>
 __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   __shared__ PushLds<R> L;
+  __shared__ R El[ELDS ? PushE<R>::MAXN + 1 : 1];
   const int tid = threadIdx.x;
   const int64_t nstep = D.ctr->step;
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
   diag_init(L.G);
   for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
+  if (ELDS)
+    for (int i = tid; i <= C.N; i += TPB) El[i] = (R)D.E[i];
   __syncthreads();
   int64_t Ns[3], nt[3];
   double pm[3];
@@ -1072,13 +1091,13 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   int buf = 0;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x, buf ^= 1) {
     if (t < nt[0]) {
-      const TileCount k = push_tile<R, 0>(C, D, L, buf, t * TILE, Ns[0], n, T0[0], pm[0]);
+      const TileCount k = push_tile<R, 0, ELDS>(C, D, L, El, buf, t * TILE, Ns[0], n, T0[0], pm[0]);
       ps += k.pushed; ae0 += k.abs0; ae1 += k.abs1;
     } else if (t < nt[0] + nt[1]) {
-      const TileCount k = push_tile<R, 1>(C, D, L, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
+      const TileCount k = push_tile<R, 1, ELDS>(C, D, L, El, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
       ps += k.pushed; an0 += k.abs0; an1 += k.abs1;
     } else {
-      const TileCount k = push_tile<R, 2>(C, D, L, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
+      const TileCount k = push_tile<R, 2, ELDS>(C, D, L, El, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
       ps += k.pushed; ap0 += k.abs0; ap1 += k.abs1;
     }
   }
