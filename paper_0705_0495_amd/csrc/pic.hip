@@ -287,7 +287,6 @@ struct Impl : Base {
     if ((rc = alloc(&D.nb, (size_t)D.nb_cap))) return rc;
     if ((rc = alloc(&D.nbc, 4))) return rc;
     if ((rc = alloc(&D.bhist, (size_t)NBUCKET))) return rc;
-    if ((rc = alloc(&D.boff, (size_t)NBUCKET + 1))) return rc;
     if ((rc = alloc(&D.perm, (size_t)D.nb_cap))) return rc;
     for (int s = 0; s < 3; s++) {
       if ((rc = alloc(&D.cand[s], (size_t)D.cap[s] + TILE))) return rc;

@@ -140,7 +140,6 @@ struct Dev {
   int32_t nb_cap, req_cap;
   int32_t* nbc;     // [4] total, per species
   int32_t* bhist;   // [NBUCKET] births per creator-id bucket
-  int32_t* boff;    // [NBUCKET+1]
   int32_t* perm;    // [nb_cap] births grouped by bucket
   Cand<R>* cand[3]; // candidates of the null-collision test: tile t of species s
                     // writes them to cand[s][t*TILE ...], wave w of the
@@ -1379,8 +1378,10 @@ __device__ __forceinline__ int block_excl_scan(int x, int32_t* wsum, int* total)
   return base + incl - x;
 }
 
+constexpr int BKEYS = 8192;  // births whose rank keys are kept in LDS
+
 template <class R>
-__device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, int32_t* part) {
+__device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, int32_t* part, uint64_t* keys) {
   const int tid = threadIdx.x;
   int B = D.nbc[0];
   if (B > D.nb_cap) B = D.nb_cap;
@@ -1407,26 +1408,34 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
     cur[tid * PER + q] = run;
     run += loc[q];
   }
-  if (tid == 0) D.boff[NBUCKET] = total;
   __syncthreads();
-  for (int i = tid; i < NBUCKET; i += TAIL_TPB) D.boff[i] = cur[i];
+  // keys grouped by bucket: in LDS when they fit, else through perm in global
+  // memory; afterwards cur[b] is the end of bucket b (= start of b + 1)
+  const bool lds = B <= BKEYS;
   const uint64_t next = (uint64_t)D.ctr->next_id;
   for (int b = tid; b < B; b += TAIL_TPB) {
-    const int bkt = birth_bucket(D.nb[b].creator, next);
+    const Birth<R> rec = D.nb[b];
+    const int bkt = birth_bucket(rec.creator, next);
     const int slot = atomicAdd(&cur[bkt], 1);
-    D.perm[slot] = b;
+    if (lds) keys[slot] = (rec.creator << 2) | (uint64_t)rec.k;
+    else D.perm[slot] = b;
   }
-  __threadfence();
   __syncthreads();
   for (int b = tid; b < B; b += TAIL_TPB) {
     const Birth<R> rec = D.nb[b];
     const uint64_t key = (rec.creator << 2) | (uint64_t)rec.k;
     const int bk = birth_bucket(rec.creator, next);
-    const int lo = D.boff[bk], hi = D.boff[bk + 1];
+    const int lo = bk > 0 ? cur[bk - 1] : 0, hi = cur[bk];
     int rank = lo;
     for (int i = lo; i < hi; i++) {
-      const Birth<R>& o = D.nb[D.perm[i]];
-      rank += (((o.creator << 2) | (uint64_t)o.k) < key);
+      uint64_t ok;
+      if (lds) {
+        ok = keys[i];
+      } else {
+        const Birth<R>& o = D.nb[D.perm[i]];
+        ok = (o.creator << 2) | (uint64_t)o.k;
+      }
+      rank += ok < key;
     }
     if (rec.sp >= 0) {
       const int sp = rec.sp;
@@ -1451,15 +1460,16 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
     int32_t cur[NBUCKET];
   } U;
   __shared__ int32_t part[TAIL_TPB];
+  __shared__ uint64_t bkeys[BKEYS];
   const int tid = threadIdx.x;
   const int64_t n = D.ctr->step;
   int nr = *D.nreq;
   if (nr > D.req_cap) nr = D.req_cap;
+  // one workgroup: its barriers order the global writes of one phase before
+  // the reads of the next (no device-scope fence needed)
   if (nr > 0) resolve_claims(C, D, U.claims, nr, (uint32_t)n);
-  __threadfence();
   __syncthreads();
-  births_phase(C, D, U.cur, part);
-  __threadfence();
+  births_phase(C, D, U.cur, part, bkeys);
   __syncthreads();
   int B = D.nbc[0];
   if (B > D.nb_cap) B = D.nb_cap;
@@ -1502,7 +1512,6 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
     if (tid == 0) D.ctr->cycles += 1;
   }
   if (!do_field) return;
-  __threadfence();
   __syncthreads();
   field_phase<R, PER>(C, D, 1, n + 1, U.field);
 }

@@ -248,3 +248,25 @@ def test_large_size_coulomb_matches_oracle():
     g.step(1)
     o.step(1)
     compare(g, o, "fp32", "large coulomb step 1")
+
+
+def test_births_above_lds_key_capacity_match_oracle():
+    """More than 8192 births in one step (hot electrons, ionisation only,
+    scaled up): birth ranks fall back from LDS keys to global memory."""
+    from tests.oracle_helpers import tables_only
+    wl = dataclasses.replace(workload("small"), n_init=(100000, 1000, 100000), T_init_eV=(30.0, 0.026, 0.026))
+    sig, thr, loss = tables_only([11])
+    o0 = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    pm = o0.constants()["pmax_e"]
+    o0.close()
+    sig = sig * (0.3 / pm)
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    o.step(1)
+    _, _, misc = o.counters()
+    assert misc["births"] > 8192, misc["births"]
+    compare(g, o, "fp32", "many births step 1")
+    g.step(2)
+    o.step(2)
+    compare(g, o, "fp32", "many births step 3")
