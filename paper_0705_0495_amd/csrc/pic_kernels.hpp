@@ -870,19 +870,27 @@ __device__ __forceinline__ void deposit_win(uint64_t* win, int32_t* cnt, int64_t
 
 struct TileCount {
   int pushed, abs0, abs1;
+  int32_t next_cell;  // first cell of the workgroup's next tile, read before this tile's barrier
 };
+
+// the deposit window of a tile starts 64 cells below its first particle's
+// cell, as that cell was before the push: every wave must use the same base,
+// so the cell is read before any wave of the workgroup can have pushed the
+// tile (at kernel start, or before the previous tile's barrier)
+__device__ __forceinline__ int win_base(int32_t first_cell) { return (first_cell == DEAD ? 0 : first_cell) - 64; }
 
 // One workgroup pushes one tile of TILE consecutive particles.  Deposits go
 // to an LDS window of WIN cells (one 64-bit LDS atomic per run of a thread's
 // particles in one cell), flushed to global memory after the tile's single
 // barrier; consecutive tiles alternate between two windows, so the next tile
 // starts while this one is flushed.  Each wave writes its candidates to its
-// own region of the list.
+// own region of the list.  next_first points at the first cell of the
+// workgroup's next tile (null if none).
 template <class R, int S, bool ELDS>
 __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, const R* El,
                                                int buf, int64_t t0, int64_t Ns, uint32_t n, uint64_t T0,
-                                               double pmax) {
-  TileCount tc = {0, 0, 0};
+                                               double pmax, int base, const int32_t* next_first) {
+  TileCount tc = {0, 0, 0, DEAD};
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int N = C.N;
@@ -890,8 +898,7 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   int32_t* cnt_s = D.cnt + (size_t)S * N;
   int64_t* F_s = D.F + (size_t)S * N;
   uint64_t* win = L.win[buf];
-  const int32_t cfirst = st.cell[t0];
-  const int base = (cfirst == DEAD ? 0 : cfirst) - 64;
+  if (next_first) tc.next_cell = *next_first;
   const int64_t s0 = t0 + (int64_t)PPT * tid;
   int32_t c[PPT];
   R off[PPT], vx[PPT];
@@ -1073,7 +1080,6 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
   if (ELDS)
     for (int i = tid; i <= C.N; i += TPB) El[i] = (R)D.E[i];
-  __syncthreads();
   int64_t Ns[3], nt[3];
   double pm[3];
   uint64_t T0[3];
@@ -1086,19 +1092,33 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
     if (Ns[s] > 0 && pm[s] > 1.0 && blockIdx.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
   }
   const int64_t total = nt[0] + nt[1] + nt[2];
+  // first cell of tile t, as stored before this workgroup pushes it
+  auto first_cell = [&](int64_t t) -> const int32_t* {
+    if (t >= total) return nullptr;
+    if (t < nt[0]) return D.st[0].cell + t * TILE;
+    if (t < nt[0] + nt[1]) return D.st[1].cell + (t - nt[0]) * TILE;
+    return D.st[2].cell + (t - nt[0] - nt[1]) * TILE;
+  };
+  int base = 0;
+  if (const int32_t* f = first_cell(blockIdx.x)) base = win_base(*f);
+  __syncthreads();
   int ps = 0, ae0 = 0, ae1 = 0, an0 = 0, an1 = 0, ap0 = 0, ap1 = 0;
   int buf = 0;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x, buf ^= 1) {
+    const int32_t* nf = first_cell(t + gridDim.x);
+    TileCount k;
     if (t < nt[0]) {
-      const TileCount k = push_tile<R, 0, ELDS>(C, D, L, El, buf, t * TILE, Ns[0], n, T0[0], pm[0]);
-      ps += k.pushed; ae0 += k.abs0; ae1 += k.abs1;
+      k = push_tile<R, 0, ELDS>(C, D, L, El, buf, t * TILE, Ns[0], n, T0[0], pm[0], base, nf);
+      ae0 += k.abs0; ae1 += k.abs1;
     } else if (t < nt[0] + nt[1]) {
-      const TileCount k = push_tile<R, 1, ELDS>(C, D, L, El, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1]);
-      ps += k.pushed; an0 += k.abs0; an1 += k.abs1;
+      k = push_tile<R, 1, ELDS>(C, D, L, El, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1], base, nf);
+      an0 += k.abs0; an1 += k.abs1;
     } else {
-      const TileCount k = push_tile<R, 2, ELDS>(C, D, L, El, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2]);
-      ps += k.pushed; ap0 += k.abs0; ap1 += k.abs1;
+      k = push_tile<R, 2, ELDS>(C, D, L, El, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2], base, nf);
+      ap0 += k.abs0; ap1 += k.abs1;
     }
+    ps += k.pushed;
+    base = win_base(k.next_cell);
   }
   // [electrode][species]
   if (ae0) atomicAdd(&L.G.absorbed[0], ae0);

@@ -175,6 +175,41 @@ def test_large_size_matches_oracle_sampled():
     compare(g, o, "fp32", "large step 1", sample_mod=997)
 
 
+def test_large_run_is_reproducible():
+    """The 2^25-particle discharge over 2000 steps (200 sorts and Coulomb
+    passes), twice: in one call on the default grid, and in chunks of 100 steps
+    on a smaller persistent grid.  Every result is a deterministic function of
+    the input (integer deposits, id-keyed random numbers), so the two runs must
+    agree bit for bit whatever order the workgroups ran in; a workgroup whose
+    waves disagreed on a shared value (the deposit window's base cell, read
+    while another wave was already storing the tile) broke this within a few
+    hundred steps."""
+    import hashlib
+    wl = workload("large")
+    sig, thr, loss = build_tables()
+    cap = [4 * n + (1 << 20) for n in wl.n_init]
+    prints = []
+    for grid, chunk in ((0, 2000), (509, 100)):
+        g = _gpu()(wl, sig, thr, loss, precision="fp32", capacity=cap)
+        if grid:
+            g.set_grid(grid)
+        for _ in range(2000 // chunk):
+            g.step(chunk)
+            g.sync()
+        m = g.moments()
+        h = hashlib.sha1()
+        for s in range(3):
+            for a in _by_id(g.particles(s)):
+                h.update(np.ascontiguousarray(a).tobytes())
+        prints.append((g.charge(), g.field()[1], m["events"], m["absorbed"], m["next_id"], h.hexdigest()))
+        g.close()
+    a, b = prints
+    assert np.array_equal(a[0], b[0]), "node charge differs"
+    assert np.array_equal(a[1], b[1]), "field differs"
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4], "counters differ"
+    assert a[5] == b[5], "particles differ"
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("lnl", [10.0, 1e4])
 def test_coulomb_matches_oracle(prec, lnl):
