@@ -32,7 +32,9 @@ NAMES = ["n_e", "n_O-", "n_O2+"]
 def gpu_run(name, k, cycles, skip):
     from paper_0705_0495_amd import Discharge
     wl = seeded(name, k)
-    g = Discharge(wl, *build_tables(), precision="fp32")
+    # room for the negative ions that attachment accumulates over the run
+    cap = [8 * n + (1 << 20) for n in wl.n_init]
+    g = Discharge(wl, *build_tables(), precision="fp32", capacity=cap)
     M = wl.steps_per_period
     last = np.zeros(19)
 
