@@ -66,6 +66,7 @@ struct Counters {
   int64_t events[NCH];
   int64_t absorbed[6];   // [electrode][species]
   int64_t psteps, births, cycles, tophits, nreq, nacc;
+  int64_t step_push;     // the step the last push advanced (read by the step's end)
   int32_t err, pad;
 };
 
@@ -1076,6 +1077,7 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   const int64_t nstep = D.ctr->step;
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
+  if (blockIdx.x == 0 && tid == 0) D.ctr->step_push = nstep;
   diag_init(L.G);
   for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
   if (ELDS)
@@ -1472,6 +1474,35 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
   }
 }
 
+// close the rf cycle: move the accumulated sums to the last-cycle buffers
+template <class R>
+__device__ void close_cycle(const Consts<R>& C, const Dev<R>& D) {
+  const int tid = threadIdx.x;
+  const int N = C.N;
+  for (int i = tid; i < 3 * (N + 1); i += TAIL_TPB) {
+    D.Qlast[i] = D.Qacc[i];
+    D.Qacc[i] = 0;
+  }
+  for (int i = tid; i <= N; i += TAIL_TPB) {
+    D.philast[i] = D.phiacc[i];
+    D.phiacc[i] = 0;
+  }
+  for (int i = tid; i <= C.eedf_bins; i += TAIL_TPB) {
+    D.eedf_last[i] = D.eedf_acc[i];
+    D.eedf_acc[i] = 0;
+  }
+  for (int i = tid; i < C.fneg_xbins * C.fneg_ebins; i += TAIL_TPB) {
+    D.fneg_last[i] = D.fneg_acc[i];
+    D.fneg_acc[i] = 0;
+  }
+  if (tid == 0) D.ctr->cycles += 1;
+}
+
+// End of step n, the step the push advanced.  Two workgroups: when no
+// partner request is pending, the second computes the field of the next step
+// (with the cycle sums) while the first places the births; with requests the
+// first does everything in order, since the claims change the deposits the
+// field is made from.
 template <class R, int PER>
 __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int do_field) {
   __shared__ union {
@@ -1482,11 +1513,20 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
   __shared__ int32_t part[TAIL_TPB];
   __shared__ uint64_t bkeys[BKEYS];
   const int tid = threadIdx.x;
-  const int64_t n = D.ctr->step;
+  const int64_t n = D.ctr->step_push;
   int nr = *D.nreq;
   if (nr > D.req_cap) nr = D.req_cap;
-  // one workgroup: its barriers order the global writes of one phase before
-  // the reads of the next (no device-scope fence needed)
+  const bool split = nr == 0 && do_field;
+  const bool cyc = (n + 1) % C.M == 0;
+  if (blockIdx.x == 1) {
+    if (!split) return;
+    if (cyc) close_cycle(C, D);
+    __syncthreads();
+    field_phase<R, PER>(C, D, 1, n + 1, U.field);
+    return;
+  }
+  // within the workgroup, barriers order the global writes of one phase
+  // before the reads of the next (no device-scope fence needed)
   if (nr > 0) resolve_claims(C, D, U.claims, nr, (uint32_t)n);
   __syncthreads();
   births_phase(C, D, U.cur, part, bkeys);
@@ -1510,27 +1550,8 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
     *D.nreq = 0;
     D.ctr->step = n + 1;
   }
-  // close the rf cycle: move the accumulated sums to the last-cycle buffers
-  if ((n + 1) % C.M == 0) {
-    const int N = C.N;
-    for (int i = tid; i < 3 * (N + 1); i += TAIL_TPB) {
-      D.Qlast[i] = D.Qacc[i];
-      D.Qacc[i] = 0;
-    }
-    for (int i = tid; i <= N; i += TAIL_TPB) {
-      D.philast[i] = D.phiacc[i];
-      D.phiacc[i] = 0;
-    }
-    for (int i = tid; i <= C.eedf_bins; i += TAIL_TPB) {
-      D.eedf_last[i] = D.eedf_acc[i];
-      D.eedf_acc[i] = 0;
-    }
-    for (int i = tid; i < C.fneg_xbins * C.fneg_ebins; i += TAIL_TPB) {
-      D.fneg_last[i] = D.fneg_acc[i];
-      D.fneg_acc[i] = 0;
-    }
-    if (tid == 0) D.ctr->cycles += 1;
-  }
+  if (split) return;
+  if (cyc) close_cycle(C, D);
   if (!do_field) return;
   __syncthreads();
   field_phase<R, PER>(C, D, 1, n + 1, U.field);
@@ -1540,13 +1561,13 @@ template <class R>
 inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_field, hipStream_t st) {
   const int per = (C.N + 1 + FIELD_TPB - 1) / FIELD_TPB;
   switch (per) {
-    case 1: hipLaunchKernelGGL((k_serial<R, 1>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    case 2: hipLaunchKernelGGL((k_serial<R, 2>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    case 3: hipLaunchKernelGGL((k_serial<R, 3>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    case 4: hipLaunchKernelGGL((k_serial<R, 4>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    case 5: hipLaunchKernelGGL((k_serial<R, 5>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    case 6: case 7: hipLaunchKernelGGL((k_serial<R, 7>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
-    default: hipLaunchKernelGGL((k_serial<R, FIELD_PER_MAX>), dim3(1), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 1: hipLaunchKernelGGL((k_serial<R, 1>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 2: hipLaunchKernelGGL((k_serial<R, 2>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 3: hipLaunchKernelGGL((k_serial<R, 3>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 4: hipLaunchKernelGGL((k_serial<R, 4>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 5: hipLaunchKernelGGL((k_serial<R, 5>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    case 6: case 7: hipLaunchKernelGGL((k_serial<R, 7>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
+    default: hipLaunchKernelGGL((k_serial<R, FIELD_PER_MAX>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
   }
   return hipGetLastError();
 }
