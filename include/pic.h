@@ -165,6 +165,29 @@ int pic_kernel_time(pic_ctx* ctx, double* push_ms, int64_t* launches);
  */
 int pic_set_grid(pic_ctx* ctx, int32_t push_workgroups);
 
+/*
+ * Graph replay (enable = 1) or eager launches (0, the default).  The launch
+ * sequence of a step repeats, with identical arguments, every P steps, P
+ * twice the least common multiple of sort_every and coulomb_every; with
+ * replay on, pic_step captures one such sequence into a HIP graph the first
+ * time it stands at a step count divisible by P, and from then on launches
+ * that graph for every whole period (steps in between run eagerly).  Results
+ * are identical either way.  Timing (pic_timing) uses eager launches.
+ * pic_set_grid and enable = 0 drop the captured graph.
+ */
+int pic_set_graphs(pic_ctx* ctx, int enable);
+
+/*
+ * Advance n independent discharges by n_steps steps each (asynchronous, like
+ * pic_step): their work is enqueued round robin, one period at a time, on
+ * each context's own stream, so that discharges run concurrently on the GPU
+ * (the batched use of the model: many voltages, pressures and gaps at once).
+ * Every discharge ends exactly as if stepped alone.  ctx[0..n) must be
+ * distinct; the first error stops the enqueueing and is returned (the other
+ * contexts may then stand at earlier steps).
+ */
+int pic_step_batch(pic_ctx* const* ctx, int n, int64_t n_steps);
+
 int pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);
 

@@ -77,6 +77,8 @@ def lib():
     L.pic_timing.argtypes = [C.c_void_p, C.c_int]
     L.pic_kernel_time.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
     L.pic_set_grid.argtypes = [C.c_void_p, C.c_int32]
+    L.pic_set_graphs.argtypes = [C.c_void_p, C.c_int]
+    L.pic_step_batch.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
     L.pic_destroy.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]
     L.pic_last_error.restype = C.c_char_p
@@ -200,6 +202,9 @@ class Discharge:
     def set_grid(self, workgroups):
         self._check(self.L.pic_set_grid(self.h, workgroups))
 
+    def set_graphs(self, enable=True):
+        self._check(self.L.pic_set_graphs(self.h, 1 if enable else 0))
+
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, 1 if enable else 0))
 
@@ -208,3 +213,19 @@ class Discharge:
         n = C.c_int64(0)
         self._check(self.L.pic_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+def step_batch(discharges, n_steps):
+    """Advance independent discharges together (pic_step_batch): each on its
+    own stream, their work interleaved so that they run concurrently."""
+    if not discharges:
+        return
+    L = discharges[0].L
+    arr = (C.c_void_p * len(discharges))(*[d.h for d in discharges])
+    rc = L.pic_step_batch(arr, len(discharges), n_steps)
+    if rc != 0:
+        for d in discharges:
+            msg = L.pic_last_error(d.h)
+            if msg:
+                raise PicError(rc, msg.decode())
+        raise PicError(rc, "")

@@ -66,6 +66,8 @@ struct Base {
   virtual int moments(pic_moments_t* m) = 0;
   virtual int read_err(int32_t* err) = 0;
   virtual void set_grid(int g) = 0;
+  virtual int set_graphs(int on) = 0;
+  virtual int64_t chunk() const = 0;
 };
 
 }  // namespace
@@ -116,11 +118,29 @@ struct Impl : Base {
   int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, ncu = 1;
   int64_t nstep = 0;  // steps enqueued
   bool elds = false;  // k_push stages the node field in LDS
+  bool graphs = false;                // replay captured step sequences
+  hipGraphExec_t gexec = nullptr;     // period() steps from a step count divisible by period()
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
   ~Impl() override {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     for (void* p : allocs) (void)hipFree(p);
   }
+
+  // steps after which the launch sequence repeats with the same arguments:
+  // the sort and Coulomb periods, doubled so that the sorts' exchanges of the
+  // two particle buffers return them to where they were
+  int64_t period() const {
+    const int64_t a = c->G.sort_every, b = c->G.coulomb_every > 0 ? c->G.coulomb_every : 1;
+    int64_t x = a, y = b;
+    while (y) {
+      const int64_t t = x % y;
+      x = y;
+      y = t;
+    }
+    return 2 * (a / x) * b;
+  }
+  int64_t chunk() const override { return graphs ? period() : (int64_t)c->G.sort_every; }
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -360,7 +380,74 @@ struct Impl : Base {
     return 0;
   }
 
-  void set_grid(int g) override { grid_push = g > 0 ? g : grid_push_default; }
+  void set_grid(int g) override {
+    grid_push = g > 0 ? g : grid_push_default;
+    drop_graph();
+  }
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+
+  int set_graphs(int on) override {
+    graphs = on != 0;
+    if (!graphs) drop_graph();
+    return 0;
+  }
+
+  // capture period() steps from the current state (the stream must be idle of
+  // other captures); the host's step count and buffers are restored after
+  int capture() {
+    const int64_t P = period();
+    const int64_t n0 = nstep;
+    Store<R> st0[3];
+    memcpy(st0, D.st, sizeof(st0));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = step_eager(P);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    nstep = n0;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(c, PIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (memcmp(st0, D.st, sizeof(st0)) != 0) {
+      (void)hipGraphDestroy(g);
+      return fail(c, PIC_EDEVICE, "captured steps did not return the particle buffers");
+    }
+    const hipError_t ei = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      gexec = nullptr;
+      return fail(c, PIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    return 0;
+  }
+
+  int step(int64_t nsteps) override {
+    if (!graphs || c->timing) return step_eager(nsteps);
+    const int64_t P = period();
+    while (nsteps > 0) {
+      const int64_t ph = nstep % P;
+      if (ph == 0 && nsteps >= P) {
+        if (!gexec) {
+          const int rc = capture();
+          if (rc) return rc;
+        }
+        HIPCHK(c, hipGraphLaunch(gexec, c->stream));
+        nstep += P;
+        nsteps -= P;
+      } else {
+        const int64_t k = ph == 0 ? nsteps : std::min(nsteps, P - ph);
+        const int rc = step_eager(k);
+        if (rc) return rc;
+        nsteps -= k;
+      }
+    }
+    return 0;
+  }
 
   int sort() {
     hipLaunchKernelGGL(k_sort_scan<R>, dim3(3), dim3(SCAN_TPB), 0, c->stream, C, D);
@@ -370,7 +457,7 @@ struct Impl : Base {
     return 0;
   }
 
-  int step(int64_t nsteps) override {
+  int step_eager(int64_t nsteps) {
     const int sort_every = c->G.sort_every;
     for (int64_t k = 0; k < nsteps; k++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -398,7 +485,7 @@ struct Impl : Base {
         if (rc) return rc;
         const int ce = c->G.coulomb_every;
         if (ce > 0 && nstep % ce == 0) {
-          HIPCHK(c, launch_coulomb(C, D, (uint32_t)(nstep - 1), ncu, c->stream));
+          HIPCHK(c, launch_coulomb(C, D, ncu, c->stream));
         }
         HIPCHK(c, launch_field(C, D, 1, c->stream));
       }
@@ -661,6 +748,35 @@ int pic_kernel_time(pic_ctx* c, double* ms, int64_t* launches) {
   c->ev_used = 0;
   *ms = c->timed_ms;
   *launches = c->timed_launches;
+  return PIC_OK;
+}
+
+int pic_set_graphs(pic_ctx* c, int enable) {
+  if (!c) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->set_graphs(enable);
+}
+
+int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
+  if (!ctx || n < 0 || steps < 0) return PIC_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!ctx[i]) return PIC_EINVAL;
+    if (ctx[i]->err) return ctx[i]->err;
+  }
+  // round robin in chunks of each context's period, so that every stream
+  // holds queued work while the others run
+  std::vector<int64_t> left((size_t)n, steps);
+  for (bool more = steps > 0; more;) {
+    more = false;
+    for (int i = 0; i < n; i++) {
+      if (left[i] == 0) continue;
+      const int64_t k = std::min(left[i], ctx[i]->impl->chunk());
+      const int rc = ctx[i]->impl->step(k);
+      if (rc) return rc;
+      left[i] -= k;
+      more = more || left[i] > 0;
+    }
+  }
   return PIC_OK;
 }
 

@@ -2125,7 +2125,8 @@ struct CoulLds {
 
 // cells with MLO < m <= M; LIST: cells above M go to the big-cell list
 template <class R, int M, int TPB, int MLO, bool LIST>
-__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t n) {
+__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
+  const uint32_t n = (uint32_t)D.ctr->step_push;
   __shared__ CoulLds<R, M, TPB> L;
   const int N = C.N;
   const int tid = threadIdx.x;
@@ -2180,7 +2181,8 @@ __global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D, uint32_t
 // COUL_MAXC): the order goes to the cell array of the sort's other buffer and
 // the collisions read and write the store directly
 template <class R>
-__global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D, uint32_t n) {
+__global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
+  const uint32_t n = (uint32_t)D.ctr->step_push;
   __shared__ uint32_t h[COUL_MAXC];
   __shared__ uint16_t list[COUL_MAXC];
   __shared__ int32_t bend[COUL_MAXC / 4];
@@ -2213,18 +2215,18 @@ __global__ void k_coul_reset(Consts<R> C, Dev<R> D) {
 // the Coulomb pass after a sort: reset of the big-cell list, cells that fit
 // in LDS, then the big cells on a persistent grid
 template <class R>
-inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, uint32_t n, int ncu, hipStream_t st) {
+inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, int ncu, hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset<R>, dim3(1), dim3(64), 0, st, C, D);
-  hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D, n);
+  hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
   if constexpr (MB > COUL_MID) {
     hipLaunchKernelGGL((k_coulomb<R, COUL_MID, COUL_MTPB, COUL_SMALL, false>), dim3(3 * C.N), dim3(COUL_MTPB), 0, st,
-                       C, D, n);
-    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_MID, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+                       C, D);
+    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_MID, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D);
   } else {
-    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D, n);
+    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D);
   }
-  hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D, n);
+  hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
   return hipGetLastError();
 }
 

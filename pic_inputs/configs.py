@@ -91,3 +91,27 @@ WORKLOADS = {
 
 def workload(name: str) -> Workload:
     return WORKLOADS[name].resolved()
+
+
+def sweep(count: int = 64, seed: int = 705049504) -> list:
+    """The batched parameter sweep: independent discharges with
+    U ~ U[50, 400] V, p ~ logU[5, 100] Pa, L ~ U[2, 6] cm,
+    N_c in {256, 512, 1024, 2048}, N ~ logU[1e5, 4e6] macro particles,
+    dt = T_rf / 4000, 13.56 MHz, sort and Coulomb every 10 steps.  Each
+    population is split charge neutrally as in the large discharge (40 % e,
+    10 % O-, 50 % O2+) and the weight makes the initial electron density
+    n_res.  Seeded: the same call gives the same discharges."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        U = float(rng.uniform(50.0, 400.0))
+        p = float(np.exp(rng.uniform(np.log(5.0), np.log(100.0))))
+        L = float(rng.uniform(0.02, 0.06))
+        nc = int(rng.choice([256, 512, 1024, 2048]))
+        n = float(np.exp(rng.uniform(np.log(1e5), np.log(4e6))))
+        ne, nn = int(round(0.4 * n)), int(round(0.1 * n))
+        wl = Workload(f"sweep{i}", L, nc, p, U, 13.56e6, 4000, 1, (ne, nn, ne + nn),
+                      sort_every=10, coulomb_every=10, seed=seed + 1 + i)
+        out.append(wl.resolved())
+    return out

@@ -305,3 +305,65 @@ def test_births_above_lds_key_capacity_match_oracle():
     g.step(2)
     o.step(2)
     compare(g, o, "fp32", "many births step 3")
+
+
+def _state(g):
+    out = [_by_id(g.particles(s)) for s in range(3)]
+    m = g.moments()
+    return out, g.charge(), g.field(), m["events"], m["absorbed"], m["next_id"], m["particle_steps"]
+
+
+def _same_state(a, b, label):
+    for s in range(3):
+        for x, y in zip(a[0][s], b[0][s]):
+            assert np.array_equal(x, y), f"{label}: species {s} differs"
+    assert np.array_equal(a[1], b[1]), f"{label}: charge differs"
+    assert np.array_equal(a[2][0], b[2][0]) and np.array_equal(a[2][1], b[2][1]), f"{label}: field differs"
+    assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]), f"{label}: counters differ"
+    assert a[5] == b[5] and a[6] == b[6], f"{label}: ids or pushes differ"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_graph_replay_matches_eager(prec):
+    """Captured step sequences (20 steps: sort and Coulomb every 10, twice)
+    replayed several times, with eager steps and synchronisation in between,
+    give the eager run's state after every chunk; partner reactions boosted so
+    that the end-of-step kernel takes both of its paths."""
+    wl = ragged_small(sort_every=10, coulomb_every=10)
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    ge = _gpu()(wl, sig, thr, loss, precision=prec)
+    gg = _gpu()(wl, sig, thr, loss, precision=prec)
+    gg.set_graphs(True)
+    done = 0
+    for k in (20, 20, 13, 27, 40, 5, 60):
+        ge.step(k)
+        gg.step(k)
+        ge.sync()
+        gg.sync()
+        done += k
+        _same_state(_state(ge), _state(gg), f"after {done} steps")
+    ge.close()
+    gg.close()
+
+
+def test_batch_matches_alone():
+    """Discharges of the batched sweep, scaled down, advanced together on
+    their own streams (graphs on) end exactly as each stepped alone."""
+    from paper_0705_0495_amd import step_batch
+    from pic_inputs import sweep
+    wls = [w.scaled(0.05, name=w.name) for w in sweep(64)[:5]]
+    sig, thr, loss = build_tables()
+    batch = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
+    for g in batch:
+        g.set_graphs(True)
+    step_batch(batch, 45)
+    step_batch(batch, 35)
+    for g in batch:
+        g.sync()
+    for w, g in zip(wls, batch):
+        alone = _gpu()(w, sig, thr, loss, precision="fp32")
+        alone.step(80)
+        alone.sync()
+        _same_state(_state(alone), _state(g), w.name)
+        alone.close()
+        g.close()
