@@ -178,13 +178,18 @@ int pic_set_grid(pic_ctx* ctx, int32_t push_workgroups);
 int pic_set_graphs(pic_ctx* ctx, int enable);
 
 /*
- * Advance n independent discharges by n_steps steps each (asynchronous, like
- * pic_step): their work is enqueued round robin, one period at a time, on
- * each context's own stream, so that discharges run concurrently on the GPU
- * (the batched use of the model: many voltages, pressures and gaps at once).
- * Every discharge ends exactly as if stepped alone.  ctx[0..n) must be
- * distinct; the first error stops the enqueueing and is returned (the other
- * contexts may then stand at earlier steps).
+ * Advance n independent discharges by n_steps steps each (the batched use of
+ * the model: many voltages, pressures, gaps and grids at once).  When the
+ * contexts share precision, sort and Coulomb periods and step count (and
+ * none is timing), every kernel of a step is launched once for all of them,
+ * with per-discharge constants and state in device tables, on ctx[0]'s
+ * stream, ordered after each context's earlier work and before its later
+ * work; this path synchronises before returning.  Otherwise the contexts'
+ * steps are enqueued round robin, one period at a time, each on its own
+ * stream (asynchronous, like pic_step).  Either way every discharge ends
+ * exactly as if stepped alone.  ctx[0..n) must be distinct; the first error
+ * stops the work and is returned (other contexts may then stand at earlier
+ * steps).
  */
 int pic_step_batch(pic_ctx* const* ctx, int n, int64_t n_steps);
 

@@ -68,6 +68,7 @@ struct Base {
   virtual void set_grid(int g) = 0;
   virtual int set_graphs(int on) = 0;
   virtual int64_t chunk() const = 0;
+  virtual int64_t steps_done() const = 0;
 };
 
 }  // namespace
@@ -141,6 +142,7 @@ struct Impl : Base {
     return 2 * (a / x) * b;
   }
   int64_t chunk() const override { return graphs ? period() : (int64_t)c->G.sort_every; }
+  int64_t steps_done() const override { return nstep; }
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -621,6 +623,125 @@ struct Impl : Base {
   }
 };
 
+// workgroup offsets of a 1-D batched grid: total workgroups split over the
+// discharges in proportion to their weights, at least one each
+void split_grid(const std::vector<double>& w, int total, int32_t* off) {
+  double sum = 0;
+  for (double x : w) sum += x;
+  off[0] = 0;
+  for (size_t i = 0; i < w.size(); i++) {
+    const int g = std::max(1, (int)std::lround(total * (w[i] / std::max(sum, 1.0))));
+    off[i + 1] = off[i] + g;
+  }
+}
+
+// Steps of n discharges of one precision, same sort and Coulomb periods and
+// same step count, as batched launches (one per kernel for all of them) on
+// ctx[0]'s stream, ordered after every context's earlier work and before its
+// later work.  Synchronising: the tables the launches read are freed at the
+// end.
+template <class R>
+int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
+  pic_ctx* c0 = ctx[0];
+  hipStream_t st = c0->stream;
+  std::vector<Impl<R>*> im((size_t)n);
+  for (int i = 0; i < n; i++) im[i] = static_cast<Impl<R>*>(ctx[i]->impl);
+  for (int i = 1; i < n; i++) {
+    hipEvent_t ev;
+    HIPCHK(c0, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(c0, hipEventRecord(ev, ctx[i]->stream));
+    HIPCHK(c0, hipStreamWaitEvent(st, ev, 0));
+    (void)hipEventDestroy(ev);
+  }
+  // constants, the device state as it is now and with the two particle
+  // buffers exchanged (after an odd number of sorts), grid offsets
+  std::vector<Consts<R>> hc((size_t)n);
+  std::vector<Dev<R>> hd(2 * (size_t)n);
+  std::vector<double> w((size_t)n);
+  std::vector<int32_t> off(4 * (size_t)(n + 1));
+  int maxN = 0;
+  bool elds = true;
+  for (int i = 0; i < n; i++) {
+    hc[i] = im[i]->C;
+    hd[i] = im[i]->D;
+    hd[n + i] = im[i]->D;
+    for (int s = 0; s < 3; s++) std::swap(hd[n + i].st[s], hd[n + i].alt[s]);
+    maxN = std::max(maxN, im[i]->C.N);
+    elds = elds && im[i]->elds;
+    const pic_geometry& G = ctx[i]->G;
+    w[i] = (double)(G.n_init[0] + G.n_init[1] + G.n_init[2]) + 1.0;
+  }
+  split_grid(w, im[0]->grid_push_default, &off[0]);
+  split_grid(w, im[0]->grid_scatter, &off[n + 1]);
+  off[2 * (n + 1)] = 0;
+  for (int i = 0; i < n; i++) off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + 3 * im[i]->C.N;
+  off[3 * (n + 1)] = 0;
+  for (int i = 0; i < n; i++) off[3 * (n + 1) + i + 1] = off[3 * (n + 1) + i] + 4;
+  const size_t bc = sizeof(Consts<R>) * n, bd = sizeof(Dev<R>) * 2 * n, bo = sizeof(int32_t) * off.size();
+  char* buf = nullptr;
+  HIPCHK(c0, hipMalloc(&buf, bc + bd + bo));
+  HIPCHK(c0, hipMemcpyAsync(buf, hc.data(), bc, hipMemcpyHostToDevice, st));
+  HIPCHK(c0, hipMemcpyAsync(buf + bc, hd.data(), bd, hipMemcpyHostToDevice, st));
+  HIPCHK(c0, hipMemcpyAsync(buf + bc + bd, off.data(), bo, hipMemcpyHostToDevice, st));
+  const Consts<R>* dC = (const Consts<R>*)buf;
+  const Dev<R>* dD[2] = {(const Dev<R>*)(buf + bc), (const Dev<R>*)(buf + bc) + n};
+  const int32_t* doff = (const int32_t*)(buf + bc + bd);
+  BatchGrids g;
+  g.push = doff;
+  g.scat = doff + (n + 1);
+  g.coul = doff + 2 * (n + 1);
+  g.big = doff + 3 * (n + 1);
+  g.n_push = off[n];
+  g.n_scat = off[(n + 1) + n];
+  g.n_coul = off[2 * (n + 1) + n];
+  g.n_big = off[3 * (n + 1) + n];
+  const int per = (maxN + 1 + FIELD_TPB - 1) / FIELD_TPB;
+  const int sort_every = c0->G.sort_every, ce = c0->G.coulomb_every;
+  int64_t nstep = im[0]->nstep;
+  int par = 0;
+  int rc = 0;
+  for (int64_t k = 0; k < steps && !rc; k++) {
+    hipError_t e = launch_push_b<R>(dC, dD[par], n, g, elds, st);
+    nstep++;
+    const bool sort_now = nstep % sort_every == 0;
+    if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, true, sort_now ? 0 : 1, st);
+    if (sort_now && e == hipSuccess) {
+      e = launch_sort_b<R>(dC, dD[par], n, g, st);
+      par ^= 1;
+      if (e == hipSuccess && ce > 0 && nstep % ce == 0) e = launch_coulomb_b<R>(dC, dD[par], n, g, st);
+      if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, false, 1, st);
+    }
+    if (e != hipSuccess) rc = fail(c0, PIC_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+  }
+  // every context stands where its own steps would have left it
+  for (int i = 0; i < n; i++) {
+    im[i]->nstep = nstep;
+    if (par)
+      for (int s = 0; s < 3; s++) std::swap(im[i]->D.st[s], im[i]->D.alt[s]);
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  if (rc) return rc;
+  if (es != hipSuccess) return fail(c0, PIC_EDEVICE, std::string("batch: ") + hipGetErrorString(es));
+  return 0;
+}
+
+// the batched path applies when every context has the same precision,
+// periods and step count, no timing and no replacement stream shared
+bool batchable(pic_ctx* const* ctx, int n) {
+  if (n < 2) return false;
+  const pic_geometry& G0 = ctx[0]->G;
+  for (int i = 0; i < n; i++) {
+    const pic_geometry& G = ctx[i]->G;
+    if (G.precision != G0.precision || G.sort_every != G0.sort_every || G.coulomb_every != G0.coulomb_every)
+      return false;
+    if (ctx[i]->timing || ctx[i]->impl->steps_done() != ctx[0]->impl->steps_done()) return false;
+    for (int j = 0; j < i; j++)
+      if (ctx[j] == ctx[i]) return false;
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -763,8 +884,10 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
     if (!ctx[i]) return PIC_EINVAL;
     if (ctx[i]->err) return ctx[i]->err;
   }
-  // round robin in chunks of each context's period, so that every stream
-  // holds queued work while the others run
+  if (steps > 0 && batchable(ctx, n))
+    return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps) : batch_run<float>(ctx, n, steps);
+  // otherwise round robin in chunks of each context's period, so that every
+  // stream holds queued work while the others run
   std::vector<int64_t> left((size_t)n, steps);
   for (bool more = steps > 0; more;) {
     more = false;

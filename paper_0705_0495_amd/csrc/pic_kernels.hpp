@@ -70,6 +70,26 @@ struct Counters {
   int32_t err, pad;
 };
 
+// a workgroup's place in the grid of one discharge: its index and the
+// number of workgroups working on that discharge
+struct Blk {
+  int x, n;
+};
+
+// in a batched launch over a 1-D grid, discharge i owns workgroups
+// [off[i], off[i + 1]); returns i and the workgroup's place within it
+__device__ __forceinline__ int batch_block(const int32_t* off, int nd, Blk& b) {
+  int lo = 0, hi = nd;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  b.x = (int)blockIdx.x - off[lo];
+  b.n = off[lo + 1] - off[lo];
+  return lo;
+}
+
 template <class R>
 struct Birth {
   int32_t sp, idx, k, cell;
@@ -602,9 +622,20 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
 }
 
 template <class R, int PER>
-__global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
+__device__ __forceinline__ void k_field_body(const Consts<R>& C, const Dev<R>& D, int mode) {
   __shared__ FieldLds FL;
   field_phase<R, PER>(C, D, mode, D.ctr->step, FL);
+}
+
+template <class R, int PER>
+__global__ void __launch_bounds__(FIELD_TPB) k_field(Consts<R> C, Dev<R> D, int mode) {
+  k_field_body<R, PER>(C, D, mode);
+}
+
+// the same for a batch of discharges, one per blockIdx.y
+template <class R, int PER>
+__global__ void __launch_bounds__(FIELD_TPB) k_field_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds, int mode) {
+  k_field_body<R, PER>(Cs[blockIdx.y], Ds[blockIdx.y], mode);
 }
 
 template <class R>
@@ -1070,14 +1101,14 @@ __device__ __forceinline__ double pmax_of(const Consts<R>& C, const Dev<R>& D, i
 // ELDS: the node field (rounded to R, the values of E2) is staged in LDS
 // and the gather reads it there; for grids up to PushE<R>::MAXN cells
 template <class R, bool ELDS>
-__global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
   __shared__ PushLds<R> L;
   __shared__ R El[ELDS ? PushE<R>::MAXN + 1 : 1];
   const int tid = threadIdx.x;
   const int64_t nstep = D.ctr->step;
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
-  if (blockIdx.x == 0 && tid == 0) D.ctr->step_push = nstep;
+  if (B.x == 0 && tid == 0) D.ctr->step_push = nstep;
   diag_init(L.G);
   for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
   if (ELDS)
@@ -1091,7 +1122,7 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
     pm[s] = pmax_of(C, D, s);
     const double t = ceil(pm[s] * 4294967296.0);
     T0[s] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
-    if (Ns[s] > 0 && pm[s] > 1.0 && blockIdx.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
+    if (Ns[s] > 0 && pm[s] > 1.0 && B.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
   }
   const int64_t total = nt[0] + nt[1] + nt[2];
   // first cell of tile t, as stored before this workgroup pushes it
@@ -1102,12 +1133,12 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
     return D.st[2].cell + (t - nt[0] - nt[1]) * TILE;
   };
   int base = 0;
-  if (const int32_t* f = first_cell(blockIdx.x)) base = win_base(*f);
+  if (const int32_t* f = first_cell(B.x)) base = win_base(*f);
   __syncthreads();
   int ps = 0, ae0 = 0, ae1 = 0, an0 = 0, an1 = 0, ap0 = 0, ap1 = 0;
   int buf = 0;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x, buf ^= 1) {
-    const int32_t* nf = first_cell(t + gridDim.x);
+  for (int64_t t = B.x; t < total; t += B.n, buf ^= 1) {
+    const int32_t* nf = first_cell(t + B.n);
     TileCount k;
     if (t < nt[0]) {
       k = push_tile<R, 0, ELDS>(C, D, L, El, buf, t * TILE, Ns[0], n, T0[0], pm[0], base, nf);
@@ -1136,17 +1167,17 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
   {
     constexpr int FB = 16;
     __shared__ int32_t cpre[FB * 4 + 1];
-    int64_t t = blockIdx.x;
+    int64_t t = B.x;
     while (t < total) {
       const int s = t < nt[0] ? 0 : (t < nt[0] + nt[1] ? 1 : 2);
       const int64_t tb = s == 0 ? 0 : (s == 1 ? nt[0] : nt[0] + nt[1]);
       const int64_t tend = tb + nt[s];
       int nbt = 0;
-      for (int64_t u = t; nbt < FB && u < tend; u += gridDim.x) nbt++;
+      for (int64_t u = t; nbt < FB && u < tend; u += B.n) nbt++;
       if (tid < 64) {
         int x = 0;
         if (tid < nbt * 4) {
-          const int64_t tile = t + (int64_t)(tid >> 2) * gridDim.x - tb;
+          const int64_t tile = t + (int64_t)(tid >> 2) * B.n - tb;
           x = D.tcnt[s][tile * 4 + (tid & 3)];
         }
 #pragma unroll
@@ -1166,28 +1197,43 @@ __global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
           if (cpre[mid] <= e) lo = mid;
           else hi = mid;
         }
-        const int64_t tile = t + (int64_t)(lo >> 2) * gridDim.x - tb;
+        const int64_t tile = t + (int64_t)(lo >> 2) * B.n - tb;
         const int64_t r = tile * TILE + (lo & 3) * WTILE + (e - cpre[lo]);
         if (s == 0) collide_one<R, 0>(C, D, L.G, r, n);
         else if (s == 1) collide_one<R, 1>(C, D, L.G, r, n);
         else collide_one<R, 2>(C, D, L.G, r, n);
       }
       __syncthreads();
-      t += (int64_t)nbt * gridDim.x;
+      t += (int64_t)nbt * B.n;
     }
   }
   diag_flush(C, D, L.G);
+}
+
+template <class R, bool ELDS>
+__global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
+  k_push_body<R, ELDS>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
+// [off[i], off[i + 1]))
+template <class R, bool ELDS>
+__global__ void __launch_bounds__(TPB) k_push_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+    const int32_t* __restrict__ off, int nd) {
+  Blk b;
+  const int i = batch_block(off, nd, b);
+  k_push_body<R, ELDS>(Cs[i], Ds[i], b);
 }
 
 // ---------------------------------------------------------------------------
 // last-workgroup detection (no spinning: the final workgroup to arrive does
 // the serial part)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool last_block(uint32_t* counter) {
+__device__ __forceinline__ bool last_block(uint32_t* counter, int grid) {
   __shared__ bool is_last;
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (uint32_t)grid - 1);
   __syncthreads();
   if (is_last) __threadfence();
   return is_last;
@@ -1504,7 +1550,7 @@ __device__ void close_cycle(const Consts<R>& C, const Dev<R>& D) {
 // first does everything in order, since the claims change the deposits the
 // field is made from.
 template <class R, int PER>
-__global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int do_field) {
+__device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& D, int do_field) {
   __shared__ union {
     FieldLds field;
     ClaimLds claims;
@@ -1557,6 +1603,17 @@ __global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int 
   field_phase<R, PER>(C, D, 1, n + 1, U.field);
 }
 
+template <class R, int PER>
+__global__ void __launch_bounds__(TAIL_TPB) k_serial(Consts<R> C, Dev<R> D, int do_field) {
+  k_serial_body<R, PER>(C, D, do_field);
+}
+
+// the same for a batch of discharges, one per blockIdx.y
+template <class R, int PER>
+__global__ void __launch_bounds__(TAIL_TPB) k_serial_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds, int do_field) {
+  k_serial_body<R, PER>(Cs[blockIdx.y], Ds[blockIdx.y], do_field);
+}
+
 template <class R>
 inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_field, hipStream_t st) {
   const int per = (C.N + 1 + FIELD_TPB - 1) / FIELD_TPB;
@@ -1579,7 +1636,7 @@ inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_fiel
 constexpr int SCAN_TPB = 1024;
 
 template <class R>
-__global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_sort_scan_body(const Consts<R>& C, const Dev<R>& D) {
   __shared__ int64_t part[SCAN_TPB];
   __shared__ int32_t pmax[SCAN_TPB];
   const int s = blockIdx.x;
@@ -1622,6 +1679,17 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
   }
 }
 
+template <class R>
+__global__ void __launch_bounds__(SCAN_TPB) k_sort_scan(Consts<R> C, Dev<R> D) {
+  k_sort_scan_body<R>(C, D);
+}
+
+// the same for a batch of discharges, one per blockIdx.y
+template <class R>
+__global__ void __launch_bounds__(SCAN_TPB) k_sort_scan_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds) {
+  k_sort_scan_body<R>(Cs[blockIdx.y], Ds[blockIdx.y]);
+}
+
 constexpr int SORT_TPB = 256;
 constexpr int SORT_PER = 4;
 constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
@@ -1648,7 +1716,7 @@ struct SortLds {
 // order inside a cell is arbitrary: no result depends on it.  Particles whose
 // cell lies outside the chunk's window take a global atomic of their own.
 template <class R>
-__global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_sort_scatter_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
   __shared__ SortLds<R> L;
   const int N = C.N;
   const int tid = threadIdx.x;
@@ -1660,7 +1728,7 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
     nch[s] = (Ns[s] + SORT_CHUNK - 1) / SORT_CHUNK;
   }
   const int64_t total = nch[0] + nch[1] + nch[2];
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  for (int64_t t = B.x; t < total; t += B.n) {
     int s = 0;
     int64_t c = t;
     if (c >= nch[0]) {
@@ -1795,11 +1863,26 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D
     }
     __syncthreads();
   }
-  if (!last_block(&D.done[2])) return;
+  if (!last_block(&D.done[2], B.n)) return;
   if (threadIdx.x == 0) {
     D.done[2] = 0;
     for (int s = 0; s < 3; s++) D.N[s] = D.Nnew[s];
   }
+}
+
+template <class R>
+__global__ void __launch_bounds__(SORT_TPB) k_sort_scatter(Consts<R> C, Dev<R> D) {
+  k_sort_scatter_body<R>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
+// [off[i], off[i + 1]))
+template <class R>
+__global__ void __launch_bounds__(SORT_TPB) k_sort_scatter_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+    const int32_t* __restrict__ off, int nd) {
+  Blk b;
+  const int i = batch_block(off, nd, b);
+  k_sort_scatter_body<R>(Cs[i], Ds[i], b);
 }
 
 // ---------------------------------------------------------------------------
@@ -2125,12 +2208,13 @@ struct CoulLds {
 
 // cells with MLO < m <= M; LIST: cells above M go to the big-cell list
 template <class R, int M, int TPB, int MLO, bool LIST>
-__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_coulomb_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
   const uint32_t n = (uint32_t)D.ctr->step_push;
   __shared__ CoulLds<R, M, TPB> L;
   const int N = C.N;
   const int tid = threadIdx.x;
-  const int w = blockIdx.x;
+  const int w = B.x;
+  if (w >= 3 * N) return;  // batches launch for their largest grid
   const int s = w / N, cell = w - s * N;
   const int32_t a = D.seg[s * (N + 1) + cell];
   const int m = D.seg[s * (N + 1) + cell + 1] - a;
@@ -2177,11 +2261,26 @@ __global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
   }
 }
 
+template <class R, int M, int TPB, int MLO, bool LIST>
+__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
+  k_coulomb_body<R, M, TPB, MLO, LIST>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
+// [off[i], off[i + 1]))
+template <class R, int M, int TPB, int MLO, bool LIST>
+__global__ void __launch_bounds__(TPB) k_coulomb_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+    const int32_t* __restrict__ off, int nd) {
+  Blk b;
+  const int i = batch_block(off, nd, b);
+  k_coulomb_body<R, M, TPB, MLO, LIST>(Cs[i], Ds[i], b);
+}
+
 // cells listed by k_coulomb (more than CoulCap<R>::M particles, at most
 // COUL_MAXC): the order goes to the cell array of the sort's other buffer and
 // the collisions read and write the store directly
 template <class R>
-__global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_coul_big_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
   const uint32_t n = (uint32_t)D.ctr->step_push;
   __shared__ uint32_t h[COUL_MAXC];
   __shared__ uint16_t list[COUL_MAXC];
@@ -2189,7 +2288,7 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
   __shared__ int32_t wsum[COUL_TPB / 64];
   const int N = C.N;
   const int nunits = min(*D.ncoul, 3 * N);
-  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+  for (int u = B.x; u < nunits; u += B.n) {
     const int w = D.coul_big[u];
     const int s = w / N, cell = w - s * N;
     const int32_t a = D.seg[s * (N + 1) + cell];
@@ -2208,8 +2307,34 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
 }
 
 template <class R>
-__global__ void k_coul_reset(Consts<R> C, Dev<R> D) {
+__global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
+  k_coul_big_body<R>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
+// [off[i], off[i + 1]))
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coul_big_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+    const int32_t* __restrict__ off, int nd) {
+  Blk b;
+  const int i = batch_block(off, nd, b);
+  k_coul_big_body<R>(Cs[i], Ds[i], b);
+}
+
+template <class R>
+__device__ __forceinline__ void k_coul_reset_body(const Consts<R>& C, const Dev<R>& D) {
   if (threadIdx.x == 0) *D.ncoul = 0;
+}
+
+template <class R>
+__global__ void k_coul_reset(Consts<R> C, Dev<R> D) {
+  k_coul_reset_body<R>(C, D);
+}
+
+// the same for a batch of discharges, one per blockIdx.y
+template <class R>
+__global__ void k_coul_reset_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds) {
+  k_coul_reset_body<R>(Cs[blockIdx.y], Ds[blockIdx.y]);
 }
 
 // the Coulomb pass after a sort: reset of the big-cell list, cells that fit
@@ -2227,6 +2352,78 @@ inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, int ncu, h
     hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D);
   }
   hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// launches of one step for a batch of nd discharges: constants and device
+// state in device arrays, one launch per kernel.  Kernels that stride a
+// discharge's particles or cells use 1-D grids split by offset tables; the
+// others use blockIdx.y as the discharge.  per is the largest field template
+// parameter of the batch (the field loops check every node against N).
+// ---------------------------------------------------------------------------
+struct BatchGrids {
+  const int32_t* push;  // [nd + 1] workgroup offsets of each discharge
+  const int32_t* scat;
+  const int32_t* coul;
+  const int32_t* big;
+  int n_push, n_scat, n_coul, n_big;  // totals
+};
+
+template <class R, int PER>
+inline void launch_serial_field_b(const Consts<R>* C, const Dev<R>* D, int nd, int do_field, int field_mode,
+                                  bool serial, hipStream_t st) {
+  if (serial) hipLaunchKernelGGL((k_serial_b<R, PER>), dim3(2, nd), dim3(TAIL_TPB), 0, st, C, D, do_field);
+  else hipLaunchKernelGGL((k_field_b<R, PER>), dim3(1, nd), dim3(FIELD_TPB), 0, st, C, D, field_mode);
+}
+
+template <class R>
+inline hipError_t launch_tail_b(const Consts<R>* C, const Dev<R>* D, int nd, int per, bool serial, int arg,
+                                hipStream_t st) {
+  switch (per) {
+    case 1: launch_serial_field_b<R, 1>(C, D, nd, arg, arg, serial, st); break;
+    case 2: launch_serial_field_b<R, 2>(C, D, nd, arg, arg, serial, st); break;
+    case 3: launch_serial_field_b<R, 3>(C, D, nd, arg, arg, serial, st); break;
+    case 4: launch_serial_field_b<R, 4>(C, D, nd, arg, arg, serial, st); break;
+    case 5: launch_serial_field_b<R, 5>(C, D, nd, arg, arg, serial, st); break;
+    case 6: case 7: launch_serial_field_b<R, 7>(C, D, nd, arg, arg, serial, st); break;
+    default: launch_serial_field_b<R, FIELD_PER_MAX>(C, D, nd, arg, arg, serial, st); break;
+  }
+  return hipGetLastError();
+}
+
+template <class R>
+inline hipError_t launch_push_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g, bool elds,
+                                hipStream_t st) {
+  if (elds) hipLaunchKernelGGL((k_push_b<R, true>), dim3(g.n_push), dim3(TPB), 0, st, C, D, g.push, nd);
+  else hipLaunchKernelGGL((k_push_b<R, false>), dim3(g.n_push), dim3(TPB), 0, st, C, D, g.push, nd);
+  return hipGetLastError();
+}
+
+template <class R>
+inline hipError_t launch_sort_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_scan_b<R>, dim3(3, nd), dim3(SCAN_TPB), 0, st, C, D);
+  hipLaunchKernelGGL(k_sort_scatter_b<R>, dim3(g.n_scat), dim3(SORT_TPB), 0, st, C, D, g.scat, nd);
+  return hipGetLastError();
+}
+
+template <class R>
+inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g,
+                                   hipStream_t st) {
+  constexpr int MB = CoulCap<R>::M;
+  hipLaunchKernelGGL(k_coul_reset_b<R>, dim3(1, nd), dim3(64), 0, st, C, D);
+  hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
+                     g.coul, nd);
+  if constexpr (MB > COUL_MID) {
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_MID, COUL_MTPB, COUL_SMALL, false>), dim3(g.n_coul), dim3(COUL_MTPB), 0,
+                       st, C, D, g.coul, nd);
+    hipLaunchKernelGGL((k_coulomb_b<R, MB, COUL_TPB, COUL_MID, true>), dim3(g.n_coul), dim3(COUL_TPB), 0, st, C, D,
+                       g.coul, nd);
+  } else {
+    hipLaunchKernelGGL((k_coulomb_b<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(g.n_coul), dim3(COUL_TPB), 0, st, C, D,
+                       g.coul, nd);
+  }
+  hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, g.big, nd);
   return hipGetLastError();
 }
 

@@ -346,12 +346,17 @@ def test_graph_replay_matches_eager(prec):
     gg.close()
 
 
-def test_batch_matches_alone():
-    """Discharges of the batched sweep, scaled down, advanced together on
-    their own streams (graphs on) end exactly as each stepped alone."""
+@pytest.mark.parametrize("mode", ["batched", "round_robin"])
+def test_batch_matches_alone(mode):
+    """Discharges of the batched sweep, scaled down, advanced together end
+    exactly as each stepped alone: with one launch per kernel for all of them
+    (same periods), and round robin on their own streams with graph replay
+    (one discharge with another sort period makes the batch mixed)."""
     from paper_0705_0495_amd import step_batch
     from pic_inputs import sweep
     wls = [w.scaled(0.05, name=w.name) for w in sweep(64)[:5]]
+    if mode == "round_robin":
+        wls[2] = dataclasses.replace(wls[2], sort_every=5, coulomb_every=5)
     sig, thr, loss = build_tables()
     batch = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
     for g in batch:
