@@ -331,6 +331,8 @@ struct Impl : Base {
     if ((rc = alloc(&D.done, 4))) return rc;
     if ((rc = alloc(&D.ncoul, 1))) return rc;
     if ((rc = alloc(&D.coul_big, 3 * (size_t)N))) return rc;
+    if ((rc = alloc(&D.ncl, 1))) return rc;
+    if ((rc = alloc(&D.clist, 3 * (size_t)N))) return rc;
 
     // drive table and cross-section table (host math, uploaded once)
     std::vector<double> U(G.steps_per_period);
@@ -675,8 +677,10 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
   split_grid(w, im[0]->grid_scatter, &off[n + 1]);
   off[2 * (n + 1)] = 0;
   for (int i = 0; i < n; i++) off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + 3 * im[i]->C.N;
+  // persistent grid over the listed Coulomb cells of all discharges: one
+  // workgroup per CU (their LDS fills one)
   off[3 * (n + 1)] = 0;
-  for (int i = 0; i < n; i++) off[3 * (n + 1) + i + 1] = off[3 * (n + 1) + i] + 4;
+  for (int i = 0; i < n; i++) off[3 * (n + 1) + i + 1] = (int32_t)(((int64_t)(i + 1) * im[0]->ncu) / n);
   const size_t bc = sizeof(Consts<R>) * n, bd = sizeof(Dev<R>) * 2 * n, bo = sizeof(int32_t) * off.size();
   char* buf = nullptr;
   HIPCHK(c0, hipMalloc(&buf, bc + bd + bo));
@@ -729,7 +733,7 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
 // the batched path applies when every context has the same precision,
 // periods and step count, no timing and no replacement stream shared
 bool batchable(pic_ctx* const* ctx, int n) {
-  if (n < 2) return false;
+  if (n < 2 || n > BATCH_MAX) return false;
   const pic_geometry& G0 = ctx[0]->G;
   for (int i = 0; i < n; i++) {
     const pic_geometry& G = ctx[i]->G;

@@ -180,8 +180,10 @@ struct Dev {
   int64_t* fneg_acc;
   int64_t* fneg_last;
   uint32_t* done;   // [4] last-workgroup counters
-  int32_t* ncoul;   // cells above COUL_SMALL particles in this Coulomb pass
+  int32_t* ncoul;   // cells above CoulCap<R>::M particles in this Coulomb pass
   int32_t* coul_big;  // [3 Nc] their (species, cell) indices
+  int32_t* ncl;     // cells listed for the largest LDS class in this pass
+  int32_t* clist;   // [3 Nc] their (species, cell) indices
 };
 
 // ---------------------------------------------------------------------------
@@ -2206,26 +2208,12 @@ struct CoulLds {
   int32_t wsum[TPB / 64];
 };
 
-// cells with MLO < m <= M; LIST: cells above M go to the big-cell list
-template <class R, int M, int TPB, int MLO, bool LIST>
-__device__ __forceinline__ void k_coulomb_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
-  const uint32_t n = (uint32_t)D.ctr->step_push;
-  __shared__ CoulLds<R, M, TPB> L;
-  const int N = C.N;
+// collisions of one cell (species s, m particles from segment position a)
+// with its velocities staged in LDS
+template <class R, int M, int TPB>
+__device__ __forceinline__ void coul_cell(const Consts<R>& C, const Dev<R>& D, CoulLds<R, M, TPB>& L, int s, int cell,
+                                          int32_t a, int m, uint32_t n) {
   const int tid = threadIdx.x;
-  const int w = B.x;
-  if (w >= 3 * N) return;  // batches launch for their largest grid
-  const int s = w / N, cell = w - s * N;
-  const int32_t a = D.seg[s * (N + 1) + cell];
-  const int m = D.seg[s * (N + 1) + cell + 1] - a;
-  if (m < 2 || m <= MLO) return;
-  if (m > M) {
-    if (LIST && tid == 0) {
-      const int k = atomicAdd(D.ncoul, 1);
-      if (k < 3 * N) D.coul_big[k] = w;
-    }
-    return;
-  }
   const Store<R> S = D.st[s];
   // the velocities are loaded with the ids and parked in registers while the
   // order is built in the LDS they will occupy
@@ -2261,6 +2249,118 @@ __device__ __forceinline__ void k_coulomb_body(const Consts<R>& C, const Dev<R>&
   }
 }
 
+// one workgroup per cell: cells with MLO < m <= M; LIST: cells above M go to
+// the list of the largest class (clist), else they are left to later kernels
+template <class R, int M, int TPB, int MLO, bool LIST>
+__device__ __forceinline__ void k_coulomb_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
+  const uint32_t n = (uint32_t)D.ctr->step_push;
+  __shared__ CoulLds<R, M, TPB> L;
+  const int N = C.N;
+  const int w = B.x;
+  if (w >= 3 * N) return;  // batches launch for their largest grid
+  const int s = w / N, cell = w - s * N;
+  const int32_t a = D.seg[s * (N + 1) + cell];
+  const int m = D.seg[s * (N + 1) + cell + 1] - a;
+  if (m < 2 || m <= MLO) return;
+  if (m > M) {
+    if (LIST && threadIdx.x == 0) {
+      const int k = atomicAdd(D.ncl, 1);
+      if (k < 3 * N) D.clist[k] = w;
+    }
+    return;
+  }
+  coul_cell<R, M, TPB>(C, D, L, s, cell, a, m, n);
+}
+
+// the cells listed for the largest class, taken by persistent workgroups
+// (few cells, and workgroups that need most of a CU's LDS); cells above M go
+// to the big-cell list
+template <class R, int M, int TPB>
+__device__ __forceinline__ void k_coul_large_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
+  const uint32_t n = (uint32_t)D.ctr->step_push;
+  __shared__ CoulLds<R, M, TPB> L;
+  const int N = C.N;
+  const int nc = min(*D.ncl, 3 * N);
+  for (int u = B.x; u < nc; u += B.n) {
+    const int w = D.clist[u];
+    const int s = w / N, cell = w - s * N;
+    const int32_t a = D.seg[s * (N + 1) + cell];
+    const int m = D.seg[s * (N + 1) + cell + 1] - a;
+    if (m > M) {
+      if (threadIdx.x == 0) {
+        const int k = atomicAdd(D.ncoul, 1);
+        if (k < 3 * N) D.coul_big[k] = w;
+      }
+      continue;
+    }
+    coul_cell<R, M, TPB>(C, D, L, s, cell, a, m, n);
+    __syncthreads();  // the next cell reuses the LDS
+  }
+}
+
+template <class R, int M, int TPB>
+__global__ void __launch_bounds__(TPB) k_coul_large(Consts<R> C, Dev<R> D) {
+  k_coul_large_body<R, M, TPB>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// Batches: the cells listed by every discharge are numbered in one sequence
+// (discharge by discharge) and taken by the persistent workgroups of a
+// single launch, so that discharges with many such cells share the GPU.
+constexpr int BATCH_MAX = 1024;  // discharges of one batched launch
+
+// prefix of the discharges' list lengths in LDS (pre[nd] = total)
+template <class R, bool BIG>
+__device__ __forceinline__ int batch_list_prefix(const Consts<R>* Cs, const Dev<R>* Ds, int nd, int32_t* pre) {
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < nd; i++) {
+      pre[i] = t;
+      t += min(BIG ? *Ds[i].ncoul : *Ds[i].ncl, 3 * Cs[i].N);
+    }
+    pre[nd] = t;
+  }
+  __syncthreads();
+  return pre[nd];
+}
+
+__device__ __forceinline__ int batch_list_owner(const int32_t* pre, int nd, int u) {
+  int lo = 0, hi = nd;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <class R, int M, int TPB>
+__global__ void __launch_bounds__(TPB) k_coul_large_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+                                                      int nd) {
+  __shared__ CoulLds<R, M, TPB> L;
+  __shared__ int32_t pre[BATCH_MAX + 1];
+  const int tot = batch_list_prefix<R, false>(Cs, Ds, nd, pre);
+  for (int u = blockIdx.x; u < tot; u += gridDim.x) {
+    const int i = batch_list_owner(pre, nd, u);
+    const Consts<R>& C = Cs[i];
+    const Dev<R>& D = Ds[i];
+    const uint32_t n = (uint32_t)D.ctr->step_push;
+    const int N = C.N;
+    const int w = D.clist[u - pre[i]];
+    const int s = w / N, cell = w - s * N;
+    const int32_t a = D.seg[s * (N + 1) + cell];
+    const int m = D.seg[s * (N + 1) + cell + 1] - a;
+    if (m > M) {
+      if (threadIdx.x == 0) {
+        const int k = atomicAdd(D.ncoul, 1);
+        if (k < 3 * N) D.coul_big[k] = w;
+      }
+      continue;
+    }
+    coul_cell<R, M, TPB>(C, D, L, s, cell, a, m, n);
+    __syncthreads();
+  }
+}
+
 template <class R, int M, int TPB, int MLO, bool LIST>
 __global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
   k_coulomb_body<R, M, TPB, MLO, LIST>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
@@ -2279,6 +2379,26 @@ __global__ void __launch_bounds__(TPB) k_coulomb_b(const Consts<R>* __restrict__
 // cells listed by k_coulomb (more than CoulCap<R>::M particles, at most
 // COUL_MAXC): the order goes to the cell array of the sort's other buffer and
 // the collisions read and write the store directly
+// one listed big cell w (species, cell index), the order kept in global memory
+template <class R>
+__device__ __forceinline__ void coul_big_cell(const Consts<R>& C, const Dev<R>& D, int w, uint32_t n, uint32_t* h,
+                                              uint16_t* list, int32_t* bend, int32_t* wsum) {
+  const int N = C.N;
+  const int s = w / N, cell = w - s * N;
+  const int32_t a = D.seg[s * (N + 1) + cell];
+  const int m = D.seg[s * (N + 1) + cell + 1] - a;
+  if (m > COUL_MAXC) {
+    if (threadIdx.x == 0) atomicOr(&D.ctr->err, ERR_COUL);
+    return;
+  }
+  const Store<R> S = D.st[s];
+  int32_t* ordg = D.alt[s].cell;
+  coul_rank<R>(C, S, a, m, 4, n, h, list, bend, wsum, nullptr, ordg);
+  coul_pairs<R>(C, D, s, cell, m, n, [&](int r) -> int { return ordg[a + r] - a; },
+                [&](int i) -> R& { return S.vx[a + i]; }, GlobVyz<R>{S, a}, COUL_TPB);
+  __syncthreads();
+}
+
 template <class R>
 __device__ __forceinline__ void k_coul_big_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
   const uint32_t n = (uint32_t)D.ctr->step_push;
@@ -2286,24 +2406,8 @@ __device__ __forceinline__ void k_coul_big_body(const Consts<R>& C, const Dev<R>
   __shared__ uint16_t list[COUL_MAXC];
   __shared__ int32_t bend[COUL_MAXC / 4];
   __shared__ int32_t wsum[COUL_TPB / 64];
-  const int N = C.N;
-  const int nunits = min(*D.ncoul, 3 * N);
-  for (int u = B.x; u < nunits; u += B.n) {
-    const int w = D.coul_big[u];
-    const int s = w / N, cell = w - s * N;
-    const int32_t a = D.seg[s * (N + 1) + cell];
-    const int m = D.seg[s * (N + 1) + cell + 1] - a;
-    if (m > COUL_MAXC) {
-      if (threadIdx.x == 0) atomicOr(&D.ctr->err, ERR_COUL);
-      continue;
-    }
-    const Store<R> S = D.st[s];
-    int32_t* ordg = D.alt[s].cell;
-    coul_rank<R>(C, S, a, m, 4, n, h, list, bend, wsum, nullptr, ordg);
-    coul_pairs<R>(C, D, s, cell, m, n, [&](int r) -> int { return ordg[a + r] - a; },
-                  [&](int i) -> R& { return S.vx[a + i]; }, GlobVyz<R>{S, a}, COUL_TPB);
-    __syncthreads();
-  }
+  const int nunits = min(*D.ncoul, 3 * C.N);
+  for (int u = B.x; u < nunits; u += B.n) coul_big_cell<R>(C, D, D.coul_big[u], n, h, list, bend, wsum);
 }
 
 template <class R>
@@ -2311,19 +2415,28 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big(Consts<R> C, Dev<R> D) {
   k_coul_big_body<R>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
 }
 
-// the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
-// [off[i], off[i + 1]))
+// the same for a batch: the big cells of every discharge in one numbering
 template <class R>
 __global__ void __launch_bounds__(COUL_TPB) k_coul_big_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
-    const int32_t* __restrict__ off, int nd) {
-  Blk b;
-  const int i = batch_block(off, nd, b);
-  k_coul_big_body<R>(Cs[i], Ds[i], b);
+                                                         int nd) {
+  __shared__ uint32_t h[COUL_MAXC];
+  __shared__ uint16_t list[COUL_MAXC];
+  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ int32_t wsum[COUL_TPB / 64];
+  __shared__ int32_t pre[BATCH_MAX + 1];
+  const int tot = batch_list_prefix<R, true>(Cs, Ds, nd, pre);
+  for (int u = blockIdx.x; u < tot; u += gridDim.x) {
+    const int i = batch_list_owner(pre, nd, u);
+    coul_big_cell<R>(Cs[i], Ds[i], Ds[i].coul_big[u - pre[i]], (uint32_t)Ds[i].ctr->step_push, h, list, bend, wsum);
+  }
 }
 
 template <class R>
 __device__ __forceinline__ void k_coul_reset_body(const Consts<R>& C, const Dev<R>& D) {
-  if (threadIdx.x == 0) *D.ncoul = 0;
+  if (threadIdx.x == 0) {
+    *D.ncoul = 0;
+    *D.ncl = 0;
+  }
 }
 
 template <class R>
@@ -2343,14 +2456,14 @@ template <class R>
 inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, int ncu, hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset<R>, dim3(1), dim3(64), 0, st, C, D);
-  hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
   if constexpr (MB > COUL_MID) {
-    hipLaunchKernelGGL((k_coulomb<R, COUL_MID, COUL_MTPB, COUL_SMALL, false>), dim3(3 * C.N), dim3(COUL_MTPB), 0, st,
+    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
+    hipLaunchKernelGGL((k_coulomb<R, COUL_MID, COUL_MTPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_MTPB), 0, st,
                        C, D);
-    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_MID, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D);
   } else {
-    hipLaunchKernelGGL((k_coulomb<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_TPB), 0, st, C, D);
+    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, true>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
   }
+  hipLaunchKernelGGL((k_coul_large<R, MB, COUL_TPB>), dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
   hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
   return hipGetLastError();
 }
@@ -2412,18 +2525,17 @@ inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, 
                                    hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset_b<R>, dim3(1, nd), dim3(64), 0, st, C, D);
-  hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
-                     g.coul, nd);
   if constexpr (MB > COUL_MID) {
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_MID, COUL_MTPB, COUL_SMALL, false>), dim3(g.n_coul), dim3(COUL_MTPB), 0,
-                       st, C, D, g.coul, nd);
-    hipLaunchKernelGGL((k_coulomb_b<R, MB, COUL_TPB, COUL_MID, true>), dim3(g.n_coul), dim3(COUL_TPB), 0, st, C, D,
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
                        g.coul, nd);
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_MID, COUL_MTPB, COUL_SMALL, true>), dim3(g.n_coul), dim3(COUL_MTPB), 0,
+                       st, C, D, g.coul, nd);
   } else {
-    hipLaunchKernelGGL((k_coulomb_b<R, MB, COUL_TPB, COUL_SMALL, true>), dim3(g.n_coul), dim3(COUL_TPB), 0, st, C, D,
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, true>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
                        g.coul, nd);
   }
-  hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, g.big, nd);
+  hipLaunchKernelGGL((k_coul_large_b<R, MB, COUL_TPB>), dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
+  hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
   return hipGetLastError();
 }
 
