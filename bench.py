@@ -44,7 +44,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40000)
     ap.add_argument("--warmup", type=int, default=8000)
-    ap.add_argument("--workload", default="large", choices=["small", "prod", "large", "sweep"])
+    ap.add_argument("--workload", default="large", choices=["small", "prod", "large", "sweep", "serve"])
+    ap.add_argument("--requests", type=int, default=64, help="serve: requests from the sweep distribution")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrivals per second (0: all at once)")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory for particle stores")
+    ap.add_argument("--max-cycles", type=int, default=2, help="serve: rf cycles per request at most")
     ap.add_argument("--discharges", type=int, default=64, help="sweep: number of discharges")
     ap.add_argument("--eager", action="store_true", help="sweep: no graph replay")
     ap.add_argument("--sequential", action="store_true", help="sweep: also time the discharges one after another")
@@ -60,6 +64,8 @@ def main():
 
     if args.workload == "sweep":
         return sweep_main(args)
+    if args.workload == "serve":
+        return serve_main(args)
     from paper_0705_0495_amd import Discharge
     from pic_inputs import build_tables, workload
 
@@ -246,6 +252,62 @@ def sweep_main(args):
     print(json.dumps(out), flush=True)
     for d in ds:
         d.close()
+
+
+def serve_main(args):
+    """The serving loop on a finite stream of requests drawn from the sweep
+    distribution (Poisson arrivals at --rate per second), each run for at
+    most --max-cycles rf cycles or to its steady-state detector, under a
+    device-memory budget.  ``value`` is the aggregate particle pushes per
+    second over the whole stream; the JSON line also gives the requests'
+    time from arrival to retirement (p50, p99)."""
+    import numpy as np
+    from paper_0705_0495_amd.serve import Request, Server
+    from pic_inputs import build_tables, sweep
+    wls = sweep(args.requests, seed=705049600)
+    rng = np.random.default_rng(705049601)
+    gaps = rng.exponential(1.0 / args.rate, size=len(wls)) if args.rate > 0 else np.zeros(len(wls))
+    tables = build_tables()
+    s = Server(tables, int(args.budget_gb * 2**30), precision=args.precision)
+    t0 = time.perf_counter()
+    t = t0
+    for i, w in enumerate(wls):
+        t += float(gaps[i])
+        s.submit(Request(i, w, max_cycles=args.max_cycles, arrival=t))
+    while s.queue or s.active:
+        if not s.active and s.queue and s.queue[0].arrival > time.perf_counter():
+            time.sleep(min(1.0, s.queue[0].arrival - time.perf_counter()))
+            continue
+        done = s.step_cycle()
+        for r in done:
+            print(f"[bench] request {r.rid} done after {r.cycles} cycles, "
+                  f"{r.t_done - r.t_arrival:.2f}s from arrival", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    lat = s.latency()
+    pushes = sum(r.pushes for r in s.results)  # the library's count, read at retirement
+    out = {
+        "metric": "particle-steps/s (gather+push+MCC+deposit)",
+        "value": round(pushes / elapsed, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serve: {len(wls)} requests from the sweep distribution, Poisson arrivals at "
+                               f"{args.rate:g}/s, at most {args.max_cycles} rf cycles each, "
+                               f"{args.budget_gb:g} GiB budget",
+                   "precision": args.precision},
+        "latency_s": {"p50": round(lat["p50_s"], 3), "p99": round(lat["p99_s"], 3)},
+        "served": lat["served"], "steady": lat["steady"], "wall_s": round(elapsed, 2),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

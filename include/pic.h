@@ -180,8 +180,10 @@ int pic_set_graphs(pic_ctx* ctx, int enable);
 /*
  * Advance n independent discharges by n_steps steps each (the batched use of
  * the model: many voltages, pressures, gaps and grids at once).  When the
- * contexts share precision, sort and Coulomb periods and step count (and
- * none is timing), every kernel of a step is launched once for all of them,
+ * contexts share precision and sort and Coulomb periods, stand at the same
+ * phase of the step sequence (step counts equal modulo the period of
+ * pic_set_graphs) and none is timing, every kernel of a step is launched once
+ * for all of them,
  * with per-discharge constants and state in device tables, on ctx[0]'s
  * stream, ordered after each context's earlier work and before its later
  * work; this path synchronises before returning.  Otherwise the contexts'

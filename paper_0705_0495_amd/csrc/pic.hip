@@ -69,6 +69,7 @@ struct Base {
   virtual int set_graphs(int on) = 0;
   virtual int64_t chunk() const = 0;
   virtual int64_t steps_done() const = 0;
+  virtual int64_t chunk_period() const = 0;
 };
 
 }  // namespace
@@ -143,6 +144,7 @@ struct Impl : Base {
   }
   int64_t chunk() const override { return graphs ? period() : (int64_t)c->G.sort_every; }
   int64_t steps_done() const override { return nstep; }
+  int64_t chunk_period() const override { return period(); }
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -701,6 +703,8 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
   g.n_big = off[3 * (n + 1) + n];
   const int per = (maxN + 1 + FIELD_TPB - 1) / FIELD_TPB;
   const int sort_every = c0->G.sort_every, ce = c0->G.coulomb_every;
+  // every context stands at the same phase of the launch sequence: the first
+  // one's step count decides the sorts and Coulomb passes for all
   int64_t nstep = im[0]->nstep;
   int par = 0;
   int rc = 0;
@@ -719,7 +723,7 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
   }
   // every context stands where its own steps would have left it
   for (int i = 0; i < n; i++) {
-    im[i]->nstep = nstep;
+    im[i]->nstep += steps;
     if (par)
       for (int s = 0; s < 3; s++) std::swap(im[i]->D.st[s], im[i]->D.alt[s]);
   }
@@ -739,7 +743,10 @@ bool batchable(pic_ctx* const* ctx, int n) {
     const pic_geometry& G = ctx[i]->G;
     if (G.precision != G0.precision || G.sort_every != G0.sort_every || G.coulomb_every != G0.coulomb_every)
       return false;
-    if (ctx[i]->timing || ctx[i]->impl->steps_done() != ctx[0]->impl->steps_done()) return false;
+    // the launch sequence is decided once for the batch: every context must
+    // stand at the same phase of it (the steps themselves may differ)
+    const int64_t P = ctx[0]->impl->chunk_period();
+    if (ctx[i]->timing || ctx[i]->impl->steps_done() % P != ctx[0]->impl->steps_done() % P) return false;
     for (int j = 0; j < i; j++)
       if (ctx[j] == ctx[i]) return false;
   }

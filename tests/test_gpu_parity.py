@@ -372,3 +372,44 @@ def test_batch_matches_alone(mode):
         _same_state(_state(alone), _state(g), w.name)
         alone.close()
         g.close()
+
+
+def test_served_discharges_match_alone():
+    """The serving loop with room for two discharges at a time: the third is
+    admitted when the first retires and then advances in the same batched
+    launches as the second, four thousand steps apart (same phase of the
+    step sequence).  Every served discharge ends exactly as stepped alone."""
+    from paper_0705_0495_amd.serve import Request, Server, bytes_needed
+    from pic_inputs import sweep
+    wls = [w.scaled(0.01, name=w.name) for w in sweep(64)[:3]]
+    tables = build_tables()
+    budget = 2 * max(bytes_needed(w, "fp32") for w in wls)
+    reqs = [Request(i, w, max_cycles=c, tol=0.0) for i, (w, c) in enumerate(zip(wls, (1, 3, 2)))]
+    served = {}
+
+    class Keep:
+        """Discharge that records its final state before the server closes it."""
+
+        def __init__(self, wl, *t, **kw):
+            self.g = _gpu()(wl, *t, **kw)
+            self.wl = wl
+
+        def __getattr__(self, k):
+            return getattr(self.g, k)
+
+        def close(self):
+            served[self.wl.name] = _state(self.g)
+            self.g.close()
+
+    from paper_0705_0495_amd import step_batch
+    s = Server(tables, budget, backend=Keep, step_batch=lambda ds, n: step_batch([d.g for d in ds], n))
+    for r in reqs:
+        s.submit(r)
+    res = s.run()
+    assert sorted((r.rid, r.cycles) for r in res) == [(0, 1), (1, 3), (2, 2)]
+    for w, c in zip(wls, (1, 3, 2)):
+        alone = _gpu()(w, *tables, precision="fp32", capacity=[4 * n + (1 << 20) for n in w.n_init])
+        alone.step(c * w.steps_per_period)
+        alone.sync()
+        _same_state(_state(alone), served[w.name], w.name)
+        alone.close()
