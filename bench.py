@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--sequential", action="store_true", help="sweep: also time the discharges one after another")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-derived push grid")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--cpu-scale", type=float, default=1.0 / 32)
     args = ap.parse_args()
@@ -77,6 +78,13 @@ def main():
     print(f"[bench] created {args.workload} ({sum(wl.n_init)} particles) in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
     done = 0
+    grid = None
+    if not args.no_autotune and args.warmup >= 1200:
+        # part of the warm-up: six 200-step trials of the push grid (results do
+        # not depend on it), the fastest kept
+        grid = d.autotune(200)
+        done = 1200
+        print(f"[bench] autotuned push grid: {grid} workgroups", file=sys.stderr, flush=True)
     chunk = 500
     while done < args.warmup:
         k = min(chunk, args.warmup - done)
@@ -166,7 +174,7 @@ def main():
                                f"{wl.voltage_V:g} V, {wl.frequency_Hz / 1e6:g} MHz, dt=T/{wl.steps_per_period}, "
                                f"{sum(wl.n_init)} macro particles {tuple(wl.n_init)}",
                    "ion_subcycle": wl.ion_subcycle, "sort_every": wl.sort_every,
-                   "coulomb_every": wl.coulomb_every, "precision": args.precision},
+                   "coulomb_every": wl.coulomb_every, "precision": args.precision, "push_grid": grid},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

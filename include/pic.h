@@ -166,6 +166,16 @@ int pic_kernel_time(pic_ctx* ctx, double* push_ms, int64_t* launches);
 int pic_set_grid(pic_ctx* ctx, int32_t push_workgroups);
 
 /*
+ * Autotuning of the launch shape: times the fused particle kernel (HIP
+ * events) over steps_per_trial steps on each of a few persistent-grid sizes
+ * (the occupancy default and 1, 2, 4, 6, 8 workgroups per CU) and keeps the
+ * fastest; *chosen (may be NULL) receives its workgroup count.  The trial
+ * steps are real steps of the discharge (6 x steps_per_trial of them, run
+ * eagerly); results do not depend on the grid, so nothing else changes.
+ */
+int pic_autotune(pic_ctx* ctx, int64_t steps_per_trial, int32_t* chosen);
+
+/*
  * Graph replay (enable = 1) or eager launches (0, the default).  The launch
  * sequence of a step repeats, with identical arguments, every P steps, P
  * twice the least common multiple of sort_every and coulomb_every; with

@@ -78,6 +78,7 @@ def lib():
     L.pic_kernel_time.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
     L.pic_set_grid.argtypes = [C.c_void_p, C.c_int32]
     L.pic_set_graphs.argtypes = [C.c_void_p, C.c_int]
+    L.pic_autotune.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
     L.pic_step_batch.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
     L.pic_destroy.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]
@@ -204,6 +205,13 @@ class Discharge:
 
     def set_graphs(self, enable=True):
         self._check(self.L.pic_set_graphs(self.h, 1 if enable else 0))
+
+    def autotune(self, steps_per_trial=200):
+        """Pick the fastest persistent grid of the push kernel by timing a few
+        (6 x steps_per_trial real steps); returns its workgroup count."""
+        g = C.c_int32(0)
+        self._check(self.L.pic_autotune(self.h, steps_per_trial, C.byref(g)))
+        return g.value
 
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, 1 if enable else 0))

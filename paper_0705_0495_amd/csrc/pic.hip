@@ -70,6 +70,7 @@ struct Base {
   virtual int64_t chunk() const = 0;
   virtual int64_t steps_done() const = 0;
   virtual int64_t chunk_period() const = 0;
+  virtual int autotune(int64_t steps, int32_t* chosen) = 0;
 };
 
 }  // namespace
@@ -145,6 +146,38 @@ struct Impl : Base {
   int64_t chunk() const override { return graphs ? period() : (int64_t)c->G.sort_every; }
   int64_t steps_done() const override { return nstep; }
   int64_t chunk_period() const override { return period(); }
+
+  // times the push kernel on a few persistent-grid sizes, steps_per_trial
+  // real steps each (results do not depend on the grid), and keeps the fastest
+  int autotune(int64_t steps, int32_t* chosen) override {
+    const bool was = c->timing;
+    std::vector<int> cand = {grid_push_default};
+    for (int k : {1, 2, 4, 6, 8}) cand.push_back(k * ncu);  // six trials in all
+    int best = grid_push_default;
+    double tbest = 1e300;
+    for (int g : cand) {
+      set_grid(g);
+      c->timing = true;
+      c->timed_ms = 0;
+      c->timed_launches = 0;
+      c->ev_used = 0;
+      int rc = step_eager(steps);
+      if (!rc) rc = drain_events();
+      if (rc) return rc;
+      const double t = c->timed_ms / (double)std::max<int64_t>(1, c->timed_launches);
+      if (t < tbest) {
+        tbest = t;
+        best = g;
+      }
+    }
+    c->timing = was;
+    c->timed_ms = 0;
+    c->timed_launches = 0;
+    c->ev_used = 0;
+    set_grid(best == grid_push_default ? 0 : best);
+    if (chosen) *chosen = best;
+    return 0;
+  }
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -912,6 +945,12 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
     }
   }
   return PIC_OK;
+}
+
+int pic_autotune(pic_ctx* c, int64_t steps_per_trial, int32_t* chosen) {
+  if (!c || steps_per_trial <= 0) return PIC_EINVAL;
+  if (c->err) return c->err;
+  return c->impl->autotune(steps_per_trial, chosen);
 }
 
 int pic_set_grid(pic_ctx* c, int32_t g) {

@@ -413,3 +413,22 @@ def test_served_discharges_match_alone():
         alone.sync()
         _same_state(_state(alone), served[w.name], w.name)
         alone.close()
+
+
+def test_autotune_changes_no_result():
+    """The grid autotuner's trial steps are ordinary steps: afterwards the
+    discharge equals a twin stepped the same number of times on the default
+    grid, and so does the next stretch on the chosen grid."""
+    wl = ragged_small()
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    a = _gpu()(wl, sig, thr, loss, precision="fp32")
+    b = _gpu()(wl, sig, thr, loss, precision="fp32")
+    g = a.autotune(10)
+    assert g > 0
+    b.step(60)
+    _same_state(_state(a), _state(b), "after tuning")
+    a.step(25)
+    b.step(25)
+    _same_state(_state(a), _state(b), "after 25 more steps")
+    a.close()
+    b.close()
