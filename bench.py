@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-derived push grid")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--cpu-scale", type=float, default=1.0 / 32)
+    ap.add_argument("--cpu-cores", type=int, default=16, help="all-cores baseline: oracle instances at most")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the discharge is not sharded "
@@ -156,6 +157,29 @@ def main():
                          f"({sum(swl.n_init)} particles), {args.cpu_steps} steps from the initial load, "
                          f"single-threaded C oracle ({args.precision})"}
         o.close()
+        # all host cores: independent copies of the same sample, one per core,
+        # stepped in threads (the oracle is C behind ctypes, which releases
+        # the GIL); created one after another, stepped together
+        import threading
+        ncores = max(1, min(len(os.sched_getaffinity(0)), args.cpu_cores))
+        steps_mc = max(1, args.cpu_steps // 2)
+        inst = [O.Oracle(swl, sig, thr, loss, precision=args.precision) for _ in range(ncores)]
+        p0 = [i.counters()[2]["psteps"] for i in inst]
+        th = [threading.Thread(target=i.step, args=(steps_mc,)) for i in inst]
+        c0 = time.perf_counter()
+        for t_ in th:
+            t_.start()
+        for t_ in th:
+            t_.join()
+        ce = time.perf_counter() - c0
+        ptot = sum(i.counters()[2]["psteps"] - q for i, q in zip(inst, p0))
+        for i in inst:
+            i.close()
+        cpu["all_cores"] = {"value": round(ptot / ce, 1), "unit": "particle-steps/s", "cores": ncores,
+                            "kind": "oracle",
+                            "sample": f"{ncores} copies of the same sample stepped {steps_mc} steps at once, "
+                                      "one thread each"}
+        print(f"[bench] oracle on {ncores} cores: {ptot / ce:.4g} particle-steps/s", file=sys.stderr, flush=True)
 
     out = {
         "metric": "particle-steps/s (gather+push+MCC+deposit)",
