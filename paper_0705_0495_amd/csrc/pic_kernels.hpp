@@ -2188,6 +2188,8 @@ struct GlobVyz {
 template <class R> struct CoulCap;
 template <> struct CoulCap<float> { static constexpr int M = 8192; };
 template <> struct CoulCap<double> { static constexpr int M = 4096; };
+constexpr int COUL_TINY = 512;   // one wave: many workgroups per CU for the many small cells
+constexpr int COUL_TTPB = 64;
 constexpr int COUL_SMALL = 2048;
 constexpr int COUL_STPB = 256;
 constexpr int COUL_MID = 5120;   // two workgroups per CU in FP32
@@ -2456,12 +2458,15 @@ template <class R>
 inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, int ncu, hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset<R>, dim3(1), dim3(64), 0, st, C, D);
+  hipLaunchKernelGGL((k_coulomb<R, COUL_TINY, COUL_TTPB, 0, false>), dim3(3 * C.N), dim3(COUL_TTPB), 0, st, C, D);
   if constexpr (MB > COUL_MID) {
-    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
+    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, COUL_TINY, false>), dim3(3 * C.N), dim3(COUL_STPB), 0, st,
+                       C, D);
     hipLaunchKernelGGL((k_coulomb<R, COUL_MID, COUL_MTPB, COUL_SMALL, true>), dim3(3 * C.N), dim3(COUL_MTPB), 0, st,
                        C, D);
   } else {
-    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, 0, true>), dim3(3 * C.N), dim3(COUL_STPB), 0, st, C, D);
+    hipLaunchKernelGGL((k_coulomb<R, COUL_SMALL, COUL_STPB, COUL_TINY, true>), dim3(3 * C.N), dim3(COUL_STPB), 0, st,
+                       C, D);
   }
   hipLaunchKernelGGL((k_coul_large<R, MB, COUL_TPB>), dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
   hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
@@ -2525,14 +2530,16 @@ inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, 
                                    hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset_b<R>, dim3(1, nd), dim3(64), 0, st, C, D);
+  hipLaunchKernelGGL((k_coulomb_b<R, COUL_TINY, COUL_TTPB, 0, false>), dim3(g.n_coul), dim3(COUL_TTPB), 0, st, C, D,
+                     g.coul, nd);
   if constexpr (MB > COUL_MID) {
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, false>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
-                       g.coul, nd);
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, COUL_TINY, false>), dim3(g.n_coul), dim3(COUL_STPB), 0,
+                       st, C, D, g.coul, nd);
     hipLaunchKernelGGL((k_coulomb_b<R, COUL_MID, COUL_MTPB, COUL_SMALL, true>), dim3(g.n_coul), dim3(COUL_MTPB), 0,
                        st, C, D, g.coul, nd);
   } else {
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, 0, true>), dim3(g.n_coul), dim3(COUL_STPB), 0, st, C, D,
-                       g.coul, nd);
+    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, COUL_TINY, true>), dim3(g.n_coul), dim3(COUL_STPB), 0,
+                       st, C, D, g.coul, nd);
   }
   hipLaunchKernelGGL((k_coul_large_b<R, MB, COUL_TPB>), dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
   hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
