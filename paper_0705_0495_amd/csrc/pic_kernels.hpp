@@ -2530,17 +2530,13 @@ inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, 
                                    hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset_b<R>, dim3(1, nd), dim3(64), 0, st, C, D);
+  // batches of many small discharges have few cells above the small class:
+  // those are listed and shared by the persistent largest-class workgroups
+  // rather than given a 512-thread launch slot per cell of every discharge
   hipLaunchKernelGGL((k_coulomb_b<R, COUL_TINY, COUL_TTPB, 0, false>), dim3(g.n_coul), dim3(COUL_TTPB), 0, st, C, D,
                      g.coul, nd);
-  if constexpr (MB > COUL_MID) {
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, COUL_TINY, false>), dim3(g.n_coul), dim3(COUL_STPB), 0,
-                       st, C, D, g.coul, nd);
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_MID, COUL_MTPB, COUL_SMALL, true>), dim3(g.n_coul), dim3(COUL_MTPB), 0,
-                       st, C, D, g.coul, nd);
-  } else {
-    hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, COUL_TINY, true>), dim3(g.n_coul), dim3(COUL_STPB), 0,
-                       st, C, D, g.coul, nd);
-  }
+  hipLaunchKernelGGL((k_coulomb_b<R, COUL_SMALL, COUL_STPB, COUL_TINY, true>), dim3(g.n_coul), dim3(COUL_STPB), 0, st,
+                     C, D, g.coul, nd);
   hipLaunchKernelGGL((k_coul_large_b<R, MB, COUL_TPB>), dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
   hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
   return hipGetLastError();
