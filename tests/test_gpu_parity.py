@@ -346,8 +346,8 @@ def test_graph_replay_matches_eager(prec):
     gg.close()
 
 
-@pytest.mark.parametrize("mode", ["batched", "round_robin"])
-def test_batch_matches_alone(mode):
+@pytest.mark.parametrize("mode,prec", [("batched", "fp32"), ("batched", "fp64"), ("round_robin", "fp32")])
+def test_batch_matches_alone(mode, prec):
     """Discharges of the batched sweep, scaled down, advanced together end
     exactly as each stepped alone: with one launch per kernel for all of them
     (same periods), and round robin on their own streams with graph replay
@@ -355,10 +355,14 @@ def test_batch_matches_alone(mode):
     from paper_0705_0495_amd import step_batch
     from pic_inputs import sweep
     wls = [w.scaled(0.05, name=w.name) for w in sweep(64)[:5]]
+    # dense cells: above the small Coulomb class (listed for the largest
+    # class) and above the largest (the big-cell path)
+    wls += [dataclasses.replace(workload("small"), n_cells=8).scaled(2.0, name="dense8"),
+            dataclasses.replace(workload("small"), n_cells=4).scaled(4.0, name="dense4")]
     if mode == "round_robin":
         wls[2] = dataclasses.replace(wls[2], sort_every=5, coulomb_every=5)
     sig, thr, loss = build_tables()
-    batch = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
+    batch = [_gpu()(w, sig, thr, loss, precision=prec) for w in wls]
     for g in batch:
         g.set_graphs(True)
     step_batch(batch, 45)
@@ -366,7 +370,7 @@ def test_batch_matches_alone(mode):
     for g in batch:
         g.sync()
     for w, g in zip(wls, batch):
-        alone = _gpu()(w, sig, thr, loss, precision="fp32")
+        alone = _gpu()(w, sig, thr, loss, precision=prec)
         alone.step(80)
         alone.sync()
         _same_state(_state(alone), _state(g), w.name)
