@@ -40,7 +40,7 @@ class Params(C.Structure):
         ("pressure_Pa", C.c_double), ("T_gas_K", C.c_double), ("metastable_frac", C.c_double),
         ("eedf_bins", C.c_int32), ("eedf_emax_eV", C.c_double), ("fneg_xbins", C.c_int32),
         ("fneg_ebins", C.c_int32), ("fneg_emax_eV", C.c_double), ("coulomb_every", C.c_int32),
-        ("coulomb_log", C.c_double),
+        ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32),
     ]
 
 
@@ -146,6 +146,7 @@ class Oracle:
         p.fneg_emax_eV = fneg_emax_eV
         p.coulomb_every = wl.coulomb_every if coulomb_every is None else coulomb_every
         p.coulomb_log = wl.coulomb_log
+        p.coulomb_inter = 1 if getattr(wl, "coulomb_inter", False) else 0
         self.params = p
         self.eedf_bins = eedf_bins
         self.nf = fneg_xbins * fneg_ebins

@@ -282,6 +282,8 @@ struct or_ctx {
   double KP[NCH];        /* tau * M_j / (A dx) for partner channels */
   double cphi, cE;
   real cc_coul[3], cc_coul_half[3]; /* Eq. (2) prefactor per particle in the cell */
+  real cc_inter[3];                  /* the same for the pairs (e, O-), (e, O2+), (O-, O2+) */
+  real fr_inter[3][2];               /* mu / m of the pair's first and second species */
   double* Udrive;        /* [M] */
   /* state */
   store st[3];
@@ -584,6 +586,21 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
     double den = (((8.0 * PI) * (EPS0 * EPS0)) * (mu * mu)) * (p->area_m2 * c->dx);
     c->cc_coul[s] = (real)(num / den);
     c->cc_coul_half[s] = (real)((0.5 * num) / den);
+  }
+  /* unlike species a, b (all singly charged): the reduced mass of the pair and
+     the lower of the two densities (W N_min / (A dx)) */
+  {
+    static const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int q = 0; q < 3; q++) {
+      double ma = c->mass[pa[q]], mb = c->mass[pb[q]];
+      double mu = (ma * mb) / (ma + mb);
+      double tc2 = c->dt * (double)(p->coulomb_every > 0 ? p->coulomb_every : 1);
+      double num = ((((QE * QE) * (QE * QE)) * p->coulomb_log) * tc2) * p->weight;
+      double den = (((8.0 * PI) * (EPS0 * EPS0)) * (mu * mu)) * (p->area_m2 * c->dx);
+      c->cc_inter[q] = (real)(num / den);
+      c->fr_inter[q][0] = (real)(mu / ma);
+      c->fr_inter[q][1] = (real)(mu / mb);
+    }
   }
   c->cphi = ((c->dx * QE) * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
   c->cE = (QE * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
@@ -964,6 +981,15 @@ typedef struct {
   int64_t idx;
 } ckey;
 
+static void ta_collide_m(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k,
+                         int sp, int64_t m, int half, real fa, real fb, double ma, double mb);
+
+/* like particles: each takes half of the change of the relative velocity */
+static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k, int sp,
+                       int64_t m, int half) {
+  ta_collide_m(c, A, B, cc, rid, n, k, sp, m, half, (real)0.5, (real)0.5, 1.0, 1.0);
+}
+
 static int ckey_cmp(const void* x, const void* y) {
   const ckey* a = (const ckey*)x;
   const ckey* b = (const ckey*)y;
@@ -975,8 +1001,8 @@ static int ckey_cmp(const void* x, const void* y) {
 /* one binary collision of A and B (equal masses); cc = Eq. (2) prefactor times the
    particle count m of the cell; randoms from Philox with counter (rid_lo, rid_hi, n, k),
    where rid = (s N + cell) 2^32 + rank of A in the cell's pairing order */
-static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k,
-                       int sp, int64_t m, int half) {
+static void ta_collide_m(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint32_t n, uint32_t k,
+                         int sp, int64_t m, int half, real fa, real fb, double ma, double mb) {
   real ux = A->v[0] - B->v[0], uy = A->v[1] - B->v[1], uz = A->v[2] - B->v[2];
   real up2 = ux * ux + uy * uy;
   real u2 = up2 + uz * uz;
@@ -1015,17 +1041,17 @@ static void ta_collide(or_ctx* c, part* A, part* B, real cc, uint64_t rid, uint3
   }
   double pb[3], pa[3], keb = 0, kea = 0;
   if (c->log) {
-    for (int d = 0; d < 3; d++) pb[d] = (double)A->v[d] + (double)B->v[d];
-    keb = ke(1.0, A->v) + ke(1.0, B->v);
+    for (int d = 0; d < 3; d++) pb[d] = ma * (double)A->v[d] + mb * (double)B->v[d];
+    keb = ke(ma, A->v) + ke(mb, B->v);
   }
+  /* the relative velocity changes by du; each particle takes its share mu/m */
   for (int d = 0; d < 3; d++) {
-    real h = (real)0.5 * du[d];
-    A->v[d] = A->v[d] + h;
-    B->v[d] = B->v[d] - h;
+    A->v[d] = A->v[d] + fa * du[d];
+    B->v[d] = B->v[d] - fb * du[d];
   }
   if (c->log && c->nlog < c->caplog) {
-    for (int d = 0; d < 3; d++) pa[d] = (double)A->v[d] + (double)B->v[d];
-    kea = ke(1.0, A->v) + ke(1.0, B->v);
+    for (int d = 0; d < 3; d++) pa[d] = ma * (double)A->v[d] + mb * (double)B->v[d];
+    kea = ke(ma, A->v) + ke(mb, B->v);
     double vx = (double)A->v[0] - B->v[0], vy = (double)A->v[1] - B->v[1], vz = (double)A->v[2] - B->v[2];
     double cosx = ((double)ux * vx + (double)uy * vy + (double)uz * vz) /
                   (sqrt((double)u2) * sqrt(vx * vx + vy * vy + vz * vz));
@@ -1084,6 +1110,79 @@ static void coulomb(or_ctx* c, uint32_t n) {
   }
 }
 
+/* the alive particles of species s grouped by cell, each cell in pairing
+   order: Philox counter (id, n, k) word 0, ties by id; start[N + 1] */
+static ckey* cell_order(or_ctx* c, int s, uint32_t n, uint32_t k, int64_t** start_out) {
+  int N = c->N;
+  store* S = &c->st[s];
+  int64_t* start = (int64_t*)calloc((size_t)N + 1, sizeof(int64_t));
+  int64_t nal = 0;
+  for (int64_t i = 0; i < S->n; i++)
+    if (S->a[i].alive) { start[S->a[i].cell + 1]++; nal++; }
+  for (int cc = 0; cc < N; cc++) start[cc + 1] += start[cc];
+  ckey* keys = (ckey*)malloc(sizeof(ckey) * (size_t)(nal > 0 ? nal : 1));
+  int64_t* fill = (int64_t*)calloc((size_t)N, sizeof(int64_t));
+  for (int64_t i = 0; i < S->n; i++) {
+    part* p = &S->a[i];
+    if (!p->alive) continue;
+    uint32_t w[4];
+    rng(c->P.seed, p->id, n, k, w);
+    ckey* q = &keys[start[p->cell] + fill[p->cell]++];
+    q->h = w[0];
+    q->id = p->id;
+    q->idx = i;
+  }
+  for (int cc = 0; cc < N; cc++)
+    if (start[cc + 1] - start[cc] > 1) qsort(keys + start[cc], (size_t)(start[cc + 1] - start[cc]), sizeof(ckey), ckey_cmp);
+  free(fill);
+  *start_out = start;
+  return keys;
+}
+
+/* Inter-species Coulomb collisions (the unlike-particle rule of the binary
+   model of Takizuka and Abe): for the pairs (e, O-), (e, O2+), (O-, O2+) in
+   turn, in each cell holding N_a and N_b particles of the two species, every
+   particle of the more numerous species (the first species on a tie)
+   collides once: the one of rank i with the particle of rank i mod N_min of
+   the other species, in increasing i, so that a particle of the less
+   numerous species collides about N_max / N_min times in a row.  Ranks in
+   each species' own pairing order (Philox k = 20); the variance of
+   tan(chi/2) is that of Eq. (2) with the reduced mass of the pair and the
+   lower density W N_min / (A dx); the velocities change by mu/m of the
+   change of the relative velocity.  Randoms: counter
+   ((q N + cell) 2^32 + i, n, 21), q the pair. */
+static void coulomb_inter(or_ctx* c, uint32_t n) {
+  static const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  int N = c->N;
+  int64_t* st[3];
+  ckey* K[3];
+  for (int s = 0; s < 3; s++) K[s] = cell_order(c, s, n, 20, &st[s]);
+  for (int q = 0; q < 3; q++) {
+    int a = pa[q], b = pb[q];
+    for (int cc = 0; cc < N; cc++) {
+      int64_t na = st[a][cc + 1] - st[a][cc], nb = st[b][cc + 1] - st[b][cc];
+      if (na == 0 || nb == 0) continue;
+      int big = na >= nb ? a : b, sml = na >= nb ? b : a;
+      int64_t nbig = na >= nb ? na : nb, nsml = na >= nb ? nb : na;
+      real fbig = c->fr_inter[q][big == a ? 0 : 1], fsml = c->fr_inter[q][big == a ? 1 : 0];
+      real cf = c->cc_inter[q] * (real)nsml;
+      const uint64_t key = (uint64_t)(q * N + cc) << 32;
+      const ckey* KB = K[big] + st[big][cc];
+      const ckey* KS = K[sml] + st[sml][cc];
+      for (int64_t i = 0; i < nbig; i++) {
+        part* A = &c->st[big].a[KB[i].idx];
+        part* B = &c->st[sml].a[KS[i % nsml].idx];
+        ta_collide_m(c, A, B, cf, key | (uint64_t)i, n, 21, 3 + q, nsml, big, fbig, fsml, c->mass[big],
+                     c->mass[sml]);
+      }
+    }
+  }
+  for (int s = 0; s < 3; s++) {
+    free(st[s]);
+    free(K[s]);
+  }
+}
+
 static int birth_cmp(const void* x, const void* y) {
   const birth* a = (const birth*)x;
   const birth* b = (const birth*)y;
@@ -1138,7 +1237,10 @@ static int one_step(or_ctx* c) {
   int rc = commit_births(c);
   if (rc) return rc;
   if ((c->step + 1) % c->P.sort_every == 0) do_sort(c);
-  if (c->P.coulomb_every > 0 && (c->step + 1) % c->P.coulomb_every == 0) coulomb(c, n);
+  if (c->P.coulomb_every > 0 && (c->step + 1) % c->P.coulomb_every == 0) {
+    coulomb(c, n);
+    if (c->P.coulomb_inter) coulomb_inter(c, n);
+  }
   if ((c->step + 1) % M == 0) {
     memcpy(c->Qlast, c->Qacc, sizeof(int64_t) * 3 * (size_t)(N + 1));
     memcpy(c->philast, c->phiacc, sizeof(double) * (size_t)(N + 1));

@@ -40,6 +40,7 @@ typedef struct {
   double fneg_emax_eV;
   int32_t coulomb_every;      /* intra-species Coulomb collisions every n2 steps, 0 = off */
   double coulomb_log;         /* ln Lambda */
+  int32_t coulomb_inter;      /* 1: inter-species Coulomb collisions after the intra-species ones */
 } or_params;
 
 typedef struct or_ctx or_ctx;

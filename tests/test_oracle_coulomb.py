@@ -196,3 +196,74 @@ def test_anisotropy_relaxes_at_the_landau_rate():
     of mu, a lost 2) misses by 2x or more."""
     r = [_relaxation_rate_ratio("fp64" if k < 2 else "fp32", 0.00125, 160, seed_offset=k + 1) for k in range(3)]
     assert 0.90 < float(np.mean(r)) < 1.05, r
+
+
+# --------------------------------------------------------------------------
+# inter-species collisions (switched on by coulomb_inter)
+# --------------------------------------------------------------------------
+MO2 = 31.998 * AMU
+MASS = (ME, M_ONEG, MO2 - ME)
+PAIRS = ((0, 1), (0, 2), (1, 2))
+
+
+def _inter_run(precision="fp64"):
+    wl = small(n_init=(3001, 1502, 2999), n_cells=32, sort_every=10, coulomb_every=10, coulomb_inter=True)
+    o = Oracle(wl, *zero_tables(), precision=precision)
+    o.log_enable(1 << 17)
+    o.step(10)
+    ev = o.log()
+    return wl, o, ev[(ev[:, 0] == 100) & (ev[:, 1] >= 3)]
+
+
+def test_inter_pairs_conserve_momentum_and_energy():
+    for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6)):
+        wl, o, ev = _inter_run(prec)
+        assert len(ev) > 1000
+        ke_b, ke_a = ev[:, 2], ev[:, 3]
+        assert np.all(np.abs(ke_a - ke_b) <= 8 * tol * ke_b)
+        pb, pa = ev[:, 4:7], ev[:, 7:10]
+        # momentum scale: the larger of the two particles' momenta
+        scale = np.sqrt(2 * ke_b * MO2)[:, None]
+        assert np.all(np.abs(pa - pb) <= 8 * tol * scale)
+        o.close()
+
+
+def test_inter_every_particle_of_the_larger_species_collides_once():
+    wl, o, ev = _inter_run()
+    cells = [np.bincount(o.particles(s)[1], minlength=wl.n_cells) for s in range(3)]
+    for q, (a, b) in enumerate(PAIRS):
+        e = ev[ev[:, 1] == 3 + q]
+        want = int(sum(max(x, y) for x, y in zip(cells[a], cells[b]) if x > 0 and y > 0))
+        assert len(e) == want, (q, len(e), want)
+        # the variance uses the smaller population of the cell
+        mins = sorted(min(x, y) for x, y in zip(cells[a], cells[b]) if x > 0 and y > 0)
+        assert set(e[:, 14].astype(int)) <= set(mins)
+    o.close()
+
+
+def test_inter_variance_is_eq2_with_reduced_mass_and_lower_density():
+    wl, o, ev = _inter_run()
+    dt = 1.0 / (wl.frequency_Hz * wl.steps_per_period)
+    dx = wl.gap_m / wl.n_cells
+    for q, (a, b) in enumerate(PAIRS):
+        e = ev[ev[:, 1] == 3 + q]
+        mu = MASS[a] * MASS[b] / (MASS[a] + MASS[b])
+        n = wl.weight * e[:, 14] / (wl.area_m2 * dx)
+        want = QE**4 * n * wl.coulomb_log * (wl.coulomb_every * dt) / (8 * math.pi * EPS0**2 * mu**2 * e[:, 13] ** 3)
+        small_angle = e[:, 11] <= 1
+        assert np.allclose(e[:, 11], want, rtol=1e-9), q
+        assert small_angle.sum() > 0
+    o.close()
+
+
+def test_inter_off_leaves_the_intra_results_alone():
+    base = small(n_init=(2001, 401, 1999), sort_every=10, coulomb_every=10)
+    runs = []
+    for inter in (False, True):
+        o = Oracle(dataclasses.replace(base, coulomb_inter=inter), *zero_tables(), precision="fp64")
+        o.step(9)
+        runs.append([o.particles(s) for s in range(3)])
+        o.close()
+    for s in range(3):
+        for x, y in zip(runs[0][s], runs[1][s]):
+            assert np.array_equal(x, y)
