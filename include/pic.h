@@ -89,6 +89,10 @@ typedef struct {
   const double* threshold_eV; /* host [PIC_NCHAN], channel closed below */
   const double* loss_eV;      /* host [PIC_NCHAN], excitation energy dE of Eq. (5) */
   double coulomb_log;         /* ln(Lambda) of Eq. (2); > 0 when coulomb_every > 0 */
+  int32_t coulomb_inter;      /* 0 or 1: after the like-species pass, unlike pairs (e,O-), (e,O2+),
+                                 (O-,O2+) collide in each cell (binary model of Takizuka and Abe,
+                                 Eq. (2) with the reduced mass and the lower of the two densities;
+                                 an extension: Sec. III names only like-species collisions) */
 } pic_gas;
 
 /*
@@ -110,7 +114,8 @@ int pic_set_stream(pic_ctx* ctx, void* hip_stream);
  * and, every sort_every steps, the cell sort, followed every coulomb_every
  * steps by the intra-species Coulomb collisions of Sec. III (binary model of
  * Takizuka and Abe, variance of tan(chi/2) from Eq. (2); at most 16384
- * particles of one species per cell, else PIC_EOVERFLOW).  Guard conditions
+ * particles of one species per cell, else PIC_EOVERFLOW) and, when the gas
+ * sets coulomb_inter, by the unlike-species pairs (same limit).  Guard conditions
  * raised on the device are reported by pic_sync.
  */
 int pic_step(pic_ctx* ctx, int64_t n_steps);

@@ -307,6 +307,22 @@ struct Impl : Base {
       C.ccoul[s] = (R)(num / den);
       C.ccoul_h[s] = (R)((0.5 * num) / den);
     }
+    // unlike pairs (e, O-), (e, O2+), (O-, O2+), all singly charged: the
+    // reduced mass of the pair; the density is that of the less numerous one
+    {
+      const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+      for (int q = 0; q < 3; q++) {
+        const double ma = mass[pa[q]], mb = mass[pb[q]];
+        const double mu = (ma * mb) / (ma + mb);
+        const double tc2 = dt * (double)(G.coulomb_every > 0 ? G.coulomb_every : 1);
+        const double num = ((((QE * QE) * (QE * QE)) * c->gas.coulomb_log) * tc2) * G.weight;
+        const double den = (((8.0 * PI_H) * (EPS0 * EPS0)) * (mu * mu)) * (G.area_m2 * dx);
+        C.cinter[q] = (R)(num / den);
+        C.finter[q][0] = (R)(mu / ma);
+        C.finter[q][1] = (R)(mu / mb);
+      }
+    }
+    C.inter = (G.coulomb_every > 0 && c->gas.coulomb_inter) ? 1 : 0;
   }
 
   int create() override {
@@ -696,10 +712,11 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
   std::vector<Dev<R>> hd(2 * (size_t)n);
   std::vector<double> w((size_t)n);
   std::vector<int32_t> off(4 * (size_t)(n + 1));
-  int maxN = 0;
+  int maxN = 0, inter_cells = 0;
   bool elds = true;
   for (int i = 0; i < n; i++) {
     hc[i] = im[i]->C;
+    if (im[i]->C.inter) inter_cells = std::max(inter_cells, im[i]->C.N);
     hd[i] = im[i]->D;
     hd[n + i] = im[i]->D;
     for (int s = 0; s < 3; s++) std::swap(hd[n + i].st[s], hd[n + i].alt[s]);
@@ -749,7 +766,7 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
     if (sort_now && e == hipSuccess) {
       e = launch_sort_b<R>(dC, dD[par], n, g, st);
       par ^= 1;
-      if (e == hipSuccess && ce > 0 && nstep % ce == 0) e = launch_coulomb_b<R>(dC, dD[par], n, g, st);
+      if (e == hipSuccess && ce > 0 && nstep % ce == 0) e = launch_coulomb_b<R>(dC, dD[par], n, g, inter_cells, st);
       if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, false, 1, st);
     }
     if (e != hipSuccess) rc = fail(c0, PIC_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
@@ -801,7 +818,8 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       g->eedf_bins > EEDF_MAX || g->fneg_xbins < 0 || g->fneg_ebins < 0 ||
       (int64_t)g->fneg_xbins * g->fneg_ebins > FNEG_MAX || (g->eedf_bins > 0 && !(g->eedf_emax_eV > 0)) ||
       (g->fneg_ebins > 0 && !(g->fneg_emax_eV > 0)) || g->coulomb_every < 0 ||
-      (g->coulomb_every > 0 && (g->coulomb_every % g->sort_every != 0 || !(gas->coulomb_log > 0))))
+      (g->coulomb_every > 0 && (g->coulomb_every % g->sort_every != 0 || !(gas->coulomb_log > 0))) ||
+      gas->coulomb_inter < 0 || gas->coulomb_inter > 1)
     return PIC_EINVAL;
   for (int s = 0; s < 3; s++)
     if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 30) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;

@@ -50,9 +50,10 @@ struct Consts {
   double PG[NCH];
   double PGtot[3];
   double cphi, cE, invdx, inv2dx;
-  int32_t eedf_bins, fneg_xbins, fneg_ebins, pad;
+  int32_t eedf_bins, fneg_xbins, fneg_ebins, inter;  // inter: unlike-species Coulomb collisions on
   R eedf_sc, fneg_sc, fneg_em;
   R ccoul[3], ccoul_h[3];   // Eq. (2) prefactor per particle in the cell: full and half interval
+  R cinter[3], finter[3][2];  // unlike pairs (e,O-), (e,O2+), (O-,O2+): Eq. (2) with the reduced mass, mu/m_a, mu/m_b
   R sinc[10], cosc[11], logc[12], ln2, sqrt2;  // series of the samplers' elementary functions
 };
 
@@ -1895,10 +1896,12 @@ __global__ void __launch_bounds__(SORT_TPB) k_sort_scatter_b(const Consts<R>* __
 constexpr int COUL_TPB = 1024;
 constexpr int COUL_MAXC = 16384;                 // particles of one species in one cell
 
-// one collision of two equal-mass particles; cc = prefactor times the cell count
+// one binary collision; cc = prefactor times the cell count.  The relative
+// velocity u = va - vb turns by the sampled angle; va takes fa and vb -fb of
+// its change (mu/m of each particle: 1/2 for like particles)
 template <class R>
-__device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R cc, uint64_t rid, uint32_t n,
-                                        uint32_t k) {
+__device__ __forceinline__ void ta_pair_m(const Consts<R>& C, R va[3], R vb[3], R cc, uint64_t rid, uint32_t n,
+                                          uint32_t k, R fa, R fb) {
   const R ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
   const R up2 = ux * ux + uy * uy;
   const R u2 = up2 + uz * uz;
@@ -1938,10 +1941,16 @@ __device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R 
   }
 #pragma unroll
   for (int d = 0; d < 3; d++) {
-    const R h = (R)0.5 * du[d];
-    va[d] = va[d] + h;
-    vb[d] = vb[d] - h;
+    va[d] = va[d] + fa * du[d];
+    vb[d] = vb[d] - fb * du[d];
   }
+}
+
+// one collision of two equal-mass particles: each takes half of the change
+template <class R>
+__device__ __forceinline__ void ta_pair(const Consts<R>& C, R va[3], R vb[3], R cc, uint64_t rid, uint32_t n,
+                                        uint32_t k) {
+  ta_pair_m<R>(C, va, vb, cc, rid, n, k, (R)0.5, (R)0.5);
 }
 
 // exclusive prefix sum of a[0..n) in LDS by one 1024-thread workgroup
@@ -1987,13 +1996,14 @@ __device__ __forceinline__ int coul_bucket(uint32_t h, int nb) { return (int)(((
 // Returns through ordp[r] (or ordg[a + r]) the position of the particle of rank r.
 template <class R>
 __device__ void coul_rank(const Consts<R>& C, const Store<R>& S, int32_t a, int m, int per, uint32_t n, uint32_t* h,
-                          uint16_t* list, int32_t* bend, int32_t* wsum, uint16_t* ordp, int32_t* ordg) {
+                          uint16_t* list, int32_t* bend, int32_t* wsum, uint16_t* ordp, int32_t* ordg,
+                          uint32_t k = 16) {
   const int tid = threadIdx.x;
   const int nb = (m + per - 1) / per;
   for (int i = tid; i < nb; i += COUL_TPB) bend[i] = 0;
   __syncthreads();
   for (int i = tid; i < m; i += COUL_TPB) {
-    const uint32_t x = rng(C, S.id[a + i], n, 16).x;
+    const uint32_t x = rng(C, S.id[a + i], n, k).x;
     h[i] = x;
     atomicAdd(&bend[coul_bucket(x, nb)], 1);
   }
@@ -2433,6 +2443,105 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big_b(const Consts<R>* __rest
   }
 }
 
+// Unlike-species Coulomb collisions of one cell, after the like-species pass:
+// the pairs (e, O-), (e, O2+), (O-, O2+) in turn.  Every particle of the more
+// numerous species of the pair (the first on a tie) collides once, the one of
+// rank i with the particle of rank i mod N_min of the other species, in
+// increasing i; so a thread per particle of the less numerous species runs
+// its partners i = j, j + N_min, ... in that order.  Ranks: each species'
+// pairing order (Philox(id, n, 20).x, ties by id), kept in the cell array of
+// the sort's other buffer.  Randoms: counter ((q N + cell) 2^32 + i, n, 21).
+// The variance of tan(chi/2) is that of Eq. (2) with the reduced mass of the
+// pair and the lower density W N_min / (A dx).
+template <class R>
+__device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>& D, int cell, uint32_t n, uint32_t* h,
+                                                uint16_t* list, int32_t* bend, int32_t* wsum) {
+  const int N = C.N;
+  int32_t a[3];
+  int m[3];
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    a[s] = D.seg[s * (N + 1) + cell];
+    m[s] = D.seg[s * (N + 1) + cell + 1] - a[s];
+  }
+  if (m[0] > COUL_MAXC || m[1] > COUL_MAXC || m[2] > COUL_MAXC) {
+    if (threadIdx.x == 0) atomicOr(&D.ctr->err, ERR_COUL);
+    return;
+  }
+  // a species meets another only if both are present
+  const bool need[3] = {m[0] > 0 && (m[1] > 0 || m[2] > 0), m[1] > 0 && (m[0] > 0 || m[2] > 0),
+                        m[2] > 0 && (m[0] > 0 || m[1] > 0)};
+#pragma unroll
+  for (int s = 0; s < 3; s++)
+    if (need[s]) coul_rank<R>(C, D.st[s], a[s], m[s], 4, n, h, list, bend, wsum, nullptr, D.alt[s].cell, 20);
+  constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2};
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    const int sa = PA[q], sb = PB[q];
+    if (m[sa] == 0 || m[sb] == 0) continue;
+    const bool abig = m[sa] >= m[sb];
+    const int big = abig ? sa : sb, sml = abig ? sb : sa;
+    const int nbig = m[big], nsml = m[sml];
+    const R fbig = C.finter[q][abig ? 0 : 1], fsml = C.finter[q][abig ? 1 : 0];
+    const R cf = C.cinter[q] * (R)nsml;
+    const uint64_t key = (uint64_t)(q * N + cell) << 32;
+    const Store<R> SB = D.st[big], SS = D.st[sml];
+    const int32_t* ob = D.alt[big].cell + a[big];
+    const int32_t* os = D.alt[sml].cell + a[sml];
+    for (int j = threadIdx.x; j < nsml; j += COUL_TPB) {
+      const int32_t pb = os[j];
+      if (pb < a[sml] || pb >= a[sml] + nsml) {  // not a permutation: ids were not unique
+        atomicOr(&D.ctr->err, ERR_COUL);
+        continue;
+      }
+      R vb[3];
+      vb[0] = SS.vx[pb];
+      ld_yz(SS, pb, vb[1], vb[2]);
+      for (int i = j; i < nbig; i += nsml) {
+        const int32_t pa = ob[i];
+        if (pa < a[big] || pa >= a[big] + nbig) {
+          atomicOr(&D.ctr->err, ERR_COUL);
+          continue;
+        }
+        R va[3];
+        va[0] = SB.vx[pa];
+        ld_yz(SB, pa, va[1], va[2]);
+        ta_pair_m<R>(C, va, vb, cf, key | (uint64_t)i, n, 21, fbig, fsml);
+        SB.vx[pa] = va[0];
+        st_yz(SB, pa, va[1], va[2]);
+      }
+      SS.vx[pb] = vb[0];
+      st_yz(SS, pb, vb[1], vb[2]);
+    }
+    __syncthreads();  // the next pair may take the same particles
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coul_inter(Consts<R> C, Dev<R> D) {
+  __shared__ uint32_t h[COUL_MAXC];
+  __shared__ uint16_t list[COUL_MAXC];
+  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ int32_t wsum[COUL_TPB / 64];
+  if (!C.inter) return;
+  coul_inter_cell<R>(C, D, blockIdx.x, (uint32_t)D.ctr->step_push, h, list, bend, wsum);
+}
+
+// the same for a batch: blockIdx.y is the discharge, the grid spans the
+// largest cell count
+template <class R>
+__global__ void __launch_bounds__(COUL_TPB) k_coul_inter_b(const Consts<R>* __restrict__ Cs,
+                                                           const Dev<R>* __restrict__ Ds) {
+  __shared__ uint32_t h[COUL_MAXC];
+  __shared__ uint16_t list[COUL_MAXC];
+  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ int32_t wsum[COUL_TPB / 64];
+  const Consts<R>& C = Cs[blockIdx.y];
+  const Dev<R>& D = Ds[blockIdx.y];
+  if (!C.inter || (int)blockIdx.x >= C.N) return;
+  coul_inter_cell<R>(C, D, blockIdx.x, (uint32_t)D.ctr->step_push, h, list, bend, wsum);
+}
+
 template <class R>
 __device__ __forceinline__ void k_coul_reset_body(const Consts<R>& C, const Dev<R>& D) {
   if (threadIdx.x == 0) {
@@ -2470,6 +2579,7 @@ inline hipError_t launch_coulomb(const Consts<R>& C, const Dev<R>& D, int ncu, h
   }
   hipLaunchKernelGGL((k_coul_large<R, MB, COUL_TPB>), dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
   hipLaunchKernelGGL(k_coul_big<R>, dim3(ncu), dim3(COUL_TPB), 0, st, C, D);
+  if (C.inter) hipLaunchKernelGGL(k_coul_inter<R>, dim3(C.N), dim3(COUL_TPB), 0, st, C, D);
   return hipGetLastError();
 }
 
@@ -2526,7 +2636,7 @@ inline hipError_t launch_sort_b(const Consts<R>* C, const Dev<R>* D, int nd, con
 }
 
 template <class R>
-inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g,
+inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g, int inter_cells,
                                    hipStream_t st) {
   constexpr int MB = CoulCap<R>::M;
   hipLaunchKernelGGL(k_coul_reset_b<R>, dim3(1, nd), dim3(64), 0, st, C, D);
@@ -2539,6 +2649,9 @@ inline hipError_t launch_coulomb_b(const Consts<R>* C, const Dev<R>* D, int nd, 
                      C, D, g.coul, nd);
   hipLaunchKernelGGL((k_coul_large_b<R, MB, COUL_TPB>), dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
   hipLaunchKernelGGL(k_coul_big_b<R>, dim3(g.n_big), dim3(COUL_TPB), 0, st, C, D, nd);
+  // inter_cells: the largest cell count of the discharges with unlike-species
+  // collisions on, 0 if none has them
+  if (inter_cells > 0) hipLaunchKernelGGL(k_coul_inter_b<R>, dim3(inter_cells, nd), dim3(COUL_TPB), 0, st, C, D);
   return hipGetLastError();
 }
 

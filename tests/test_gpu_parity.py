@@ -285,6 +285,90 @@ def test_large_size_coulomb_matches_oracle():
     compare(g, o, "fp32", "large coulomb step 1")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("lnl", [10.0, 1e4])
+def test_inter_species_coulomb_matches_oracle(prec, lnl):
+    """Unlike-species Coulomb collisions after the like-species pass, with
+    every sort: cells where either species of a pair is the more numerous,
+    ties, and cells where one species is absent; ln Lambda = 1e4 also takes
+    the isotropic branch."""
+    wl = ragged_small(sort_every=5, coulomb_every=5, coulomb_log=lnl, coulomb_inter=True)
+    sig, thr, loss = build_tables(partner_boost=3e6)
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    done = 0
+    for target in (5, 10, 25):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, prec, f"inter coulomb step {done}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_inter_species_coulomb_long_chains_match_oracle(prec):
+    """Few O- among thousands of electrons and ions per cell: every O-
+    collides about a hundred times in a row, and a species above 1024 per
+    cell gives a workgroup thread several partners' chains."""
+    wl = dataclasses.replace(workload("small"), n_cells=8, n_init=(30001, 301, 20001), sort_every=2,
+                             coulomb_every=2, coulomb_inter=True)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    for k in range(2):
+        g.step(2)
+        o.step(2)
+        compare(g, o, prec, f"inter coulomb chains step {2 * (k + 1)}")
+
+
+def test_inter_species_coulomb_off_leaves_like_pass_alone():
+    """The switch off gives exactly the like-species results; on, the state
+    differs (the unlike pairs did collide)."""
+    base = ragged_small(sort_every=5, coulomb_every=5)
+    sig, thr, loss = build_tables()
+    off = _gpu()(base, sig, thr, loss, precision="fp32")
+    on = _gpu()(dataclasses.replace(base, coulomb_inter=True), sig, thr, loss, precision="fp32")
+    o = O.Oracle(base, sig, thr, loss, precision="fp32")
+    for d in (off, on):
+        d.step(10)
+    o.step(10)
+    compare(off, o, "fp32", "inter off step 10")
+    assert not np.array_equal(_by_id(off.particles(0))[3], _by_id(on.particles(0))[3])
+
+
+def test_large_size_inter_species_coulomb_matches_oracle():
+    """The 2^25-particle discharge with the sort and both Coulomb passes in its
+    first step; every particle compared."""
+    wl = dataclasses.replace(workload("large"), sort_every=1, coulomb_every=1, coulomb_inter=True)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    o.step(1)
+    compare(g, o, "fp32", "large inter coulomb step 1")
+
+
+def test_inter_species_coulomb_batch_matches_alone():
+    """A batch mixing discharges with the unlike-species pass on and off (one
+    launch per kernel) ends exactly as each stepped alone."""
+    from paper_0705_0495_amd import step_batch
+    sig, thr, loss = build_tables()
+    base = ragged_small(sort_every=5, coulomb_every=5)
+    wls = [dataclasses.replace(base, coulomb_inter=True, name="inter"),
+           dataclasses.replace(base, name="like"),
+           dataclasses.replace(base, n_cells=24, coulomb_inter=True, name="inter24")]
+    batch = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
+    step_batch(batch, 20)
+    for g in batch:
+        g.sync()
+    for w, g in zip(wls, batch):
+        alone = _gpu()(w, sig, thr, loss, precision="fp32")
+        alone.step(20)
+        alone.sync()
+        _same_state(_state(alone), _state(g), w.name)
+        alone.close()
+        g.close()
+
+
 def test_births_above_lds_key_capacity_match_oracle():
     """More than 8192 births in one step (hot electrons, ionisation only,
     scaled up): birth ranks fall back from LDS keys to global memory."""
