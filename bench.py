@@ -25,6 +25,7 @@ kernel's measured HBM bytes per launch (rocprofv3 counters, profiles/).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -55,6 +56,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-derived push grid")
+    ap.add_argument("--coulomb-inter", action="store_true",
+                    help="large/prod/small: unlike-species Coulomb collisions as well (off in the paper's runs)")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--cpu-scale", type=float, default=1.0 / 32)
     ap.add_argument("--cpu-cores", type=int, default=16, help="all-cores baseline: oracle instances at most")
@@ -72,6 +75,8 @@ def main():
     from pic_inputs import build_tables, workload
 
     wl = workload(args.workload)
+    if args.coulomb_inter:
+        wl = dataclasses.replace(wl, coulomb_inter=True)
     sig, thr, loss = build_tables()
     t0 = time.time()
     cap = [4 * n + (1 << 20) for n in wl.n_init]
@@ -198,7 +203,8 @@ def main():
                                f"{wl.voltage_V:g} V, {wl.frequency_Hz / 1e6:g} MHz, dt=T/{wl.steps_per_period}, "
                                f"{sum(wl.n_init)} macro particles {tuple(wl.n_init)}",
                    "ion_subcycle": wl.ion_subcycle, "sort_every": wl.sort_every,
-                   "coulomb_every": wl.coulomb_every, "precision": args.precision, "push_grid": grid},
+                   "coulomb_every": wl.coulomb_every, "coulomb_inter": bool(wl.coulomb_inter),
+                   "precision": args.precision, "push_grid": grid},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -2443,6 +2443,83 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big_b(const Consts<R>* __rest
   }
 }
 
+// The parts of a binary collision that do not depend on the velocities,
+// from the Philox words w: the Gaussian factor of tan(chi/2) (before the
+// variance), the isotropic branch's sin and 1 - cos of chi, and the azimuth.
+// ta_apply finishes the collision exactly as ta_pair_m does.
+template <class R>
+struct TaPre {
+  R nrm, sti, omci, cph, sph;
+};
+template <class R>
+__device__ __forceinline__ TaPre<R> ta_pre(const Consts<R>& C, uint4 w) {
+  TaPre<R> p;
+  p.nrm = bm_radius<R>(C, unif<R>(w.x)) * cos2pi<R>(C, unif<R>(w.y));
+  const R ct = (R)1 - (R)2 * unif<R>(w.w);
+  p.sti = Sqrt((R)1 - ct * ct);
+  p.omci = (R)1 - ct;
+  sincos2pi<R>(C, unif<R>(w.z), p.sph, p.cph);
+  return p;
+}
+template <class R>
+__device__ __forceinline__ void ta_apply(R va[3], R vb[3], R cc, R nrm, R sti, R omci, R cph, R sph, R fa, R fb) {
+  const R ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
+  const R up2 = ux * ux + uy * uy;
+  const R u2 = up2 + uz * uz;
+  if (!(u2 > (R)0)) return;
+  const R u = Sqrt(u2);
+  const R var = cc / (u2 * u);
+  R st, omc;
+  if (var > (R)1) {
+    st = sti;
+    omc = omci;
+  } else {
+    const R d = Sqrt(var) * nrm;
+    const R d2 = d * d;
+    const R inv = (R)1 / ((R)1 + d2);
+    st = (d + d) * inv;
+    omc = (d2 + d2) * inv;
+  }
+  const R s1 = st * cph, s2 = st * sph;
+  R du[3];
+  if (up2 > (R)0) {
+    const R up = Sqrt(up2);
+    const R iup = (R)1 / up;
+    const R r = uz * s1, t = u * s2;
+    du[0] = (ux * r - uy * t) * iup - ux * omc;
+    du[1] = (uy * r + ux * t) * iup - uy * omc;
+    du[2] = -(up * s1) - uz * omc;
+  } else {
+    du[0] = u * s1;
+    du[1] = u * s2;
+    du[2] = -(u * omc);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    va[d] = va[d] + fa * du[d];
+    vb[d] = vb[d] - fb * du[d];
+  }
+}
+
+// collisions of the unlike pass staged per chunk of ICH partners
+template <class R> struct InterChunk { static constexpr int ICH = sizeof(R) == 4 ? 2048 : 1024; };
+
+// LDS of the unlike pass: the ranking's arrays, then the staged chunk
+template <class R>
+union InterLds {
+  struct {
+    uint32_t h[COUL_MAXC];
+    uint16_t list[COUL_MAXC];
+    int32_t bend[COUL_MAXC / 4];
+  } r;
+  struct {
+    R vx[InterChunk<R>::ICH], vy[InterChunk<R>::ICH], vz[InterChunk<R>::ICH];
+    R nrm[InterChunk<R>::ICH], sti[InterChunk<R>::ICH], omci[InterChunk<R>::ICH];
+    R cph[InterChunk<R>::ICH], sph[InterChunk<R>::ICH];
+    int32_t pos[InterChunk<R>::ICH];
+  } c;
+};
+
 // Unlike-species Coulomb collisions of one cell, after the like-species pass:
 // the pairs (e, O-), (e, O2+), (O-, O2+) in turn.  Every particle of the more
 // numerous species of the pair (the first on a tie) collides once, the one of
@@ -2453,10 +2530,19 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_big_b(const Consts<R>* __rest
 // the sort's other buffer.  Randoms: counter ((q N + cell) 2^32 + i, n, 21).
 // The variance of tan(chi/2) is that of Eq. (2) with the reduced mass of the
 // pair and the lower density W N_min / (A dx).
+//
+// When N_min <= COUL_TPB (the long chains: a few particles of one species
+// among thousands of the other, as in the sheaths) the partners are taken in
+// chunks: the workgroup stages their velocities in LDS and computes the parts
+// of each collision that do not depend on velocities, then each chain runs
+// through the chunk on LDS alone.  Larger N_min (chains of at most
+// COUL_MAXC / COUL_TPB links) collide directly in global memory.
 template <class R>
-__device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>& D, int cell, uint32_t n, uint32_t* h,
-                                                uint16_t* list, int32_t* bend, int32_t* wsum) {
+__device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>& D, int cell, uint32_t n,
+                                                InterLds<R>& L, int32_t* wsum) {
+  constexpr int ICH = InterChunk<R>::ICH;
   const int N = C.N;
+  const int tid = threadIdx.x;
   int32_t a[3];
   int m[3];
 #pragma unroll
@@ -2465,7 +2551,7 @@ __device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>
     m[s] = D.seg[s * (N + 1) + cell + 1] - a[s];
   }
   if (m[0] > COUL_MAXC || m[1] > COUL_MAXC || m[2] > COUL_MAXC) {
-    if (threadIdx.x == 0) atomicOr(&D.ctr->err, ERR_COUL);
+    if (tid == 0) atomicOr(&D.ctr->err, ERR_COUL);
     return;
   }
   // a species meets another only if both are present
@@ -2473,58 +2559,130 @@ __device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>
                         m[2] > 0 && (m[0] > 0 || m[1] > 0)};
 #pragma unroll
   for (int s = 0; s < 3; s++)
-    if (need[s]) coul_rank<R>(C, D.st[s], a[s], m[s], 4, n, h, list, bend, wsum, nullptr, D.alt[s].cell, 20);
+    if (need[s])
+      coul_rank<R>(C, D.st[s], a[s], m[s], 4, n, L.r.h, L.r.list, L.r.bend, wsum, nullptr, D.alt[s].cell, 20);
   constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2};
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     const int sa = PA[q], sb = PB[q];
-    if (m[sa] == 0 || m[sb] == 0) continue;
-    const bool abig = m[sa] >= m[sb];
-    const int big = abig ? sa : sb, sml = abig ? sb : sa;
-    const int nbig = m[big], nsml = m[sml];
+    const int na = m[sa], nb = m[sb];
+    if (na == 0 || nb == 0) continue;
+    const bool abig = na >= nb;
+    const int nbig = abig ? na : nb, nsml = abig ? nb : na;
+    const int32_t abg = abig ? a[sa] : a[sb], asm_ = abig ? a[sb] : a[sa];
     const R fbig = C.finter[q][abig ? 0 : 1], fsml = C.finter[q][abig ? 1 : 0];
     const R cf = C.cinter[q] * (R)nsml;
     const uint64_t key = (uint64_t)(q * N + cell) << 32;
-    const Store<R> SB = D.st[big], SS = D.st[sml];
-    const int32_t* ob = D.alt[big].cell + a[big];
-    const int32_t* os = D.alt[sml].cell + a[sml];
-    for (int j = threadIdx.x; j < nsml; j += COUL_TPB) {
-      const int32_t pb = os[j];
-      if (pb < a[sml] || pb >= a[sml] + nsml) {  // not a permutation: ids were not unique
-        atomicOr(&D.ctr->err, ERR_COUL);
-        continue;
+    const Store<R> SB = D.st[abig ? sa : sb], SS = D.st[abig ? sb : sa];
+    const int32_t* ob = D.alt[abig ? sa : sb].cell + abg;
+    const int32_t* os = D.alt[abig ? sb : sa].cell + asm_;
+    if (nsml <= COUL_TPB) {
+      const bool own = tid < nsml;
+      int32_t pb = -1;
+      R vb[3] = {(R)0, (R)0, (R)0};
+      if (own) {
+        pb = os[tid];
+        if (pb < asm_ || pb >= asm_ + nsml) {  // not a permutation: ids were not unique
+          atomicOr(&D.ctr->err, ERR_COUL);
+          pb = -1;
+        } else {
+          vb[0] = SS.vx[pb];
+          ld_yz(SS, pb, vb[1], vb[2]);
+        }
       }
-      R vb[3];
-      vb[0] = SS.vx[pb];
-      ld_yz(SS, pb, vb[1], vb[2]);
-      for (int i = j; i < nbig; i += nsml) {
-        const int32_t pa = ob[i];
-        if (pa < a[big] || pa >= a[big] + nbig) {
+      for (int c0 = 0; c0 < nbig; c0 += ICH) {
+        const int cn = min(ICH, nbig - c0);
+        for (int t = tid; t < cn; t += COUL_TPB) {
+          const int i = c0 + t;
+          int32_t pa = ob[i];
+          if (pa < abg || pa >= abg + nbig) {
+            atomicOr(&D.ctr->err, ERR_COUL);
+            pa = -1;
+          }
+          L.c.pos[t] = pa;
+          R y = (R)0, z = (R)0;
+          if (pa >= 0) {
+            L.c.vx[t] = SB.vx[pa];
+            ld_yz(SB, pa, y, z);
+          }
+          L.c.vy[t] = y;
+          L.c.vz[t] = z;
+          const TaPre<R> p = ta_pre<R>(C, rng(C, key | (uint64_t)i, n, 21));
+          L.c.nrm[t] = p.nrm;
+          L.c.sti[t] = p.sti;
+          L.c.omci[t] = p.omci;
+          L.c.cph[t] = p.cph;
+          L.c.sph[t] = p.sph;
+        }
+        __syncthreads();
+        if (own && pb >= 0) {
+          int i = tid >= c0 ? tid : tid + ((c0 - tid + nsml - 1) / nsml) * nsml;
+          for (; i < c0 + cn; i += nsml) {
+            const int t = i - c0;
+            if (L.c.pos[t] < 0) continue;
+            R va[3] = {L.c.vx[t], L.c.vy[t], L.c.vz[t]};
+            ta_apply<R>(va, vb, cf, L.c.nrm[t], L.c.sti[t], L.c.omci[t], L.c.cph[t], L.c.sph[t], fbig, fsml);
+            L.c.vx[t] = va[0];
+            L.c.vy[t] = va[1];
+            L.c.vz[t] = va[2];
+          }
+        }
+        __syncthreads();
+        for (int t = tid; t < cn; t += COUL_TPB) {
+          const int32_t pa = L.c.pos[t];
+          if (pa >= 0) {
+            SB.vx[pa] = L.c.vx[t];
+            st_yz(SB, pa, L.c.vy[t], L.c.vz[t]);
+          }
+        }
+        // the next chunk's staging writes slots only this thread reads here
+      }
+      if (own && pb >= 0) {
+        SS.vx[pb] = vb[0];
+        st_yz(SS, pb, vb[1], vb[2]);
+      }
+    } else {
+      for (int j = tid; j < nsml; j += COUL_TPB) {
+        const int32_t pb = os[j];
+        if (pb < asm_ || pb >= asm_ + nsml) {
           atomicOr(&D.ctr->err, ERR_COUL);
           continue;
         }
-        R va[3];
-        va[0] = SB.vx[pa];
-        ld_yz(SB, pa, va[1], va[2]);
-        ta_pair_m<R>(C, va, vb, cf, key | (uint64_t)i, n, 21, fbig, fsml);
-        SB.vx[pa] = va[0];
-        st_yz(SB, pa, va[1], va[2]);
+        R vb[3];
+        vb[0] = SS.vx[pb];
+        ld_yz(SS, pb, vb[1], vb[2]);
+        for (int i = j; i < nbig; i += nsml) {
+          const int32_t pa = ob[i];
+          if (pa < abg || pa >= abg + nbig) {
+            atomicOr(&D.ctr->err, ERR_COUL);
+            continue;
+          }
+          R va[3];
+          va[0] = SB.vx[pa];
+          ld_yz(SB, pa, va[1], va[2]);
+          ta_pair_m<R>(C, va, vb, cf, key | (uint64_t)i, n, 21, fbig, fsml);
+          SB.vx[pa] = va[0];
+          st_yz(SB, pa, va[1], va[2]);
+        }
+        SS.vx[pb] = vb[0];
+        st_yz(SS, pb, vb[1], vb[2]);
       }
-      SS.vx[pb] = vb[0];
-      st_yz(SS, pb, vb[1], vb[2]);
     }
     __syncthreads();  // the next pair may take the same particles
   }
 }
 
+// the cells of the two sheaths hold the longest chains: workgroup b takes
+// cell b/2 from the left electrode (b even) or from the right (b odd), so
+// both start in the first wave of workgroups
+__device__ __forceinline__ int inter_cell_of(int b, int N) { return (b & 1) ? N - 1 - (b >> 1) : (b >> 1); }
+
 template <class R>
 __global__ void __launch_bounds__(COUL_TPB) k_coul_inter(Consts<R> C, Dev<R> D) {
-  __shared__ uint32_t h[COUL_MAXC];
-  __shared__ uint16_t list[COUL_MAXC];
-  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ InterLds<R> L;
   __shared__ int32_t wsum[COUL_TPB / 64];
   if (!C.inter) return;
-  coul_inter_cell<R>(C, D, blockIdx.x, (uint32_t)D.ctr->step_push, h, list, bend, wsum);
+  coul_inter_cell<R>(C, D, inter_cell_of(blockIdx.x, C.N), (uint32_t)D.ctr->step_push, L, wsum);
 }
 
 // the same for a batch: blockIdx.y is the discharge, the grid spans the
@@ -2532,14 +2690,12 @@ __global__ void __launch_bounds__(COUL_TPB) k_coul_inter(Consts<R> C, Dev<R> D) 
 template <class R>
 __global__ void __launch_bounds__(COUL_TPB) k_coul_inter_b(const Consts<R>* __restrict__ Cs,
                                                            const Dev<R>* __restrict__ Ds) {
-  __shared__ uint32_t h[COUL_MAXC];
-  __shared__ uint16_t list[COUL_MAXC];
-  __shared__ int32_t bend[COUL_MAXC / 4];
+  __shared__ InterLds<R> L;
   __shared__ int32_t wsum[COUL_TPB / 64];
   const Consts<R>& C = Cs[blockIdx.y];
   const Dev<R>& D = Ds[blockIdx.y];
   if (!C.inter || (int)blockIdx.x >= C.N) return;
-  coul_inter_cell<R>(C, D, blockIdx.x, (uint32_t)D.ctr->step_push, h, list, bend, wsum);
+  coul_inter_cell<R>(C, D, inter_cell_of(blockIdx.x, C.N), (uint32_t)D.ctr->step_push, L, wsum);
 }
 
 template <class R>
