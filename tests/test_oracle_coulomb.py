@@ -253,6 +253,12 @@ def test_inter_variance_is_eq2_with_reduced_mass_and_lower_density():
         small_angle = e[:, 11] <= 1
         assert np.allclose(e[:, 11], want, rtol=1e-9), q
         assert small_angle.sum() > 0
+        # the realised deflection of the relative velocity (it changes by the
+        # full du, mu/m_a + mu/m_b = 1): tan(chi/2) Gaussian of that variance
+        z = e[small_angle, 12] / e[small_angle, 11]
+        res = scipy.stats.kstest(z, scipy.stats.chi2(df=1).cdf)
+        assert res.pvalue > 1e-3, (q, res)
+        assert abs(np.mean(z) - 1.0) < 0.08, q
     o.close()
 
 
