@@ -209,7 +209,25 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if wl.coulomb_inter:
+        inter_chains(d, wl)
     d.close()
+
+
+def inter_chains(d, wl):
+    """Unlike-species Coulomb pass: the particle of the less numerous species
+    of a pair collides ceil(N_max / N_min) times in a row.  Prints, from the
+    final cell populations, the longest of these sequential chains per pair."""
+    import numpy as np
+    cnt = [np.bincount(d.particles(s)[1], minlength=wl.n_cells) for s in range(3)]
+    for q, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
+        na, nb = cnt[a], cnt[b]
+        both = (na > 0) & (nb > 0)
+        chain = np.where(both, -(-np.maximum(na, nb) // np.maximum(np.minimum(na, nb), 1)), 0)
+        i = int(np.argmax(chain))
+        print(f"[bench] unlike pair {('e,O-', 'e,O2+', 'O-,O2+')[q]}: longest chain {int(chain.max())} links in cell {i} "
+              f"({int(na[i])} and {int(nb[i])} particles), {int((chain > 100).sum())} cells above 100 links, "
+              f"median {np.median(chain[both]) if both.any() else 0:.0f}", file=sys.stderr, flush=True)
 
 
 def sweep_main(args):
