@@ -45,7 +45,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40000)
     ap.add_argument("--warmup", type=int, default=8000)
-    ap.add_argument("--workload", default="large", choices=["small", "prod", "large", "sweep", "serve"])
+    ap.add_argument("--workload", default="large", choices=["small", "prod", "large", "sweep", "serve", "ablation"])
+    ap.add_argument("--cycles", type=int, default=20, help="ablation: rf cycles per run")
     ap.add_argument("--requests", type=int, default=64, help="serve: requests from the sweep distribution")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrivals per second (0: all at once)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory for particle stores")
@@ -71,6 +72,8 @@ def main():
         return sweep_main(args)
     if args.workload == "serve":
         return serve_main(args)
+    if args.workload == "ablation":
+        return ablation_main(args)
     from paper_0705_0495_amd import Discharge
     from pic_inputs import build_tables, workload
 
@@ -228,6 +231,65 @@ def inter_chains(d, wl):
         print(f"[bench] unlike pair {('e,O-', 'e,O2+', 'O-,O2+')[q]}: longest chain {int(chain.max())} links in cell {i} "
               f"({int(na[i])} and {int(nb[i])} particles), {int((chain > 100).sum())} cells above 100 links, "
               f"median {np.median(chain[both]) if both.any() else 0:.0f}", file=sys.stderr, flush=True)
+
+
+def ablation_main(args):
+    """The metastable ablation pair (Sec. IV): the production discharge run
+    with C = 0 (no associative detachment) and with C = 1/6, from the same
+    seeded load, for --cycles rf cycles each.  Reports the cycle-averaged
+    macro-particle counts of the last cycle and the aggregate throughput."""
+    import numpy as np
+    from paper_0705_0495_amd import Discharge
+    from pic_inputs import build_tables, workload
+    sig, thr, loss = build_tables()
+    base = workload("prod")
+    n = base.n_cells
+    vol = np.full(n + 1, base.area_m2 * base.gap_m / n)
+    vol[[0, -1]] *= 0.5
+    runs, psteps, elapsed = {}, 0, 0.0
+    for C in (0.0, 1.0 / 6.0):
+        wl = dataclasses.replace(base, metastable_frac=C)
+        d = Discharge(wl, sig, thr, loss, precision=args.precision, capacity=[4 * x + (1 << 20) for x in wl.n_init])
+        d.set_graphs(True)
+        d.sync()
+        t0 = time.perf_counter()
+        for k in range(args.cycles):
+            d.step(wl.steps_per_period)
+            d.sync()
+            print(f"[bench] C={C:.4g} cycle {k + 1}/{args.cycles}", file=sys.stderr, flush=True)
+        elapsed += time.perf_counter() - t0
+        m = d.moments()
+        psteps += m["particle_steps"]
+        dens = np.asarray(m["density"])
+        runs[f"C={C:.4g}"] = {
+            "e": round(float((dens[0] * vol).sum() / wl.weight)),
+            "O-": round(float((dens[1] * vol).sum() / wl.weight)),
+            "O2+": round(float((dens[2] * vol).sum() / wl.weight)),
+            "associative_detachments": int(m["events"][16]),
+        }
+        print(f"[bench] C={C:.4g}: {runs[f'C={C:.4g}']}", file=sys.stderr, flush=True)
+        d.close()
+    value = psteps / elapsed
+    out = {
+        "metric": "particle-steps/s (gather+push+MCC+deposit)",
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": 2 * args.cycles * base.steps_per_period,
+        "warmup": 0,
+        "ms_per_step": round(elapsed * 1e3 / (2 * args.cycles * base.steps_per_period), 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ablation: prod discharge ({base.gap_m * 100:g} cm, {n} cells, "
+                               f"{base.pressure_Pa:g} Pa, {base.voltage_V:g} V) with C = 0 and C = 1/6, "
+                               f"{args.cycles} rf cycles each from the same seeded load",
+                   "precision": args.precision},
+        "ablation": {"cycles": args.cycles, "last_cycle_mean_macro_particles": runs},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def sweep_main(args):

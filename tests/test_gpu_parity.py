@@ -369,6 +369,26 @@ def test_inter_species_coulomb_batch_matches_alone():
         g.close()
 
 
+def test_metastable_ablation_matches_oracle():
+    """The ablation pair of the metastable fraction: C = 0 closes associative
+    detachment (no events on either side), C = 1/6 (the default, tested
+    throughout) keeps it; both discharges match the oracle."""
+    for C in (0.0, 1.0 / 6.0):
+        wl = ragged_small(metastable_frac=C, pressure_Pa=100.0)
+        sig, thr, loss = build_tables()
+        g = _gpu()(wl, sig, thr, loss, precision="fp32")
+        o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+        done = 0
+        for target in (5, 30):
+            g.step(target - done)
+            o.step(target - done)
+            done = target
+            compare(g, o, "fp32", f"C={C:g} step {done}")
+        ad = g.moments()["events"][16]
+        assert (ad == 0) if C == 0.0 else (ad > 0), (C, ad)
+        g.close()
+
+
 def test_births_above_lds_key_capacity_match_oracle():
     """More than 8192 births in one step (hot electrons, ionisation only,
     scaled up): birth ranks fall back from LDS keys to global memory."""

@@ -295,13 +295,16 @@ def test_electron_channel_rates_fp64(T_eV):
     assert checked >= (8 if T_eV < 5 else 10)
 
 
+@pytest.mark.parametrize("C", [0.0, 1.0 / 6.0, 1.0 / 3.0])
 @pytest.mark.parametrize("T_eV", [0.026, 1.0])
-def test_associative_detachment_rate_is_distribution_free(T_eV):
+def test_associative_detachment_rate_is_distribution_free(T_eV, C):
     """sigma_ad g = const (the paper's K_ad ~ const): the AD rate per O- is
-    C n_O2 K_ad for any O- distribution, K_ad = 5.96e-20 m^2 sqrt(2e/mu)."""
+    C n_O2 K_ad for any O- distribution, K_ad = 5.96e-20 m^2 sqrt(2e/mu);
+    linear in the metastable fraction C, and none at all for C = 0 (the
+    ablation pair C = 0 / C = 1/6 of Sec. IV)."""
     nn = 100_000
     wl = quiet(small(n_init=(0, nn, 0), pressure_Pa=100.0, steps_per_period=100,
-                     T_init_eV=(3.0, T_eV, 0.026)), weight=1e-30)
+                     T_init_eV=(3.0, T_eV, 0.026), metastable_frac=C), weight=1e-30)
     sig, thr, loss = tables_only([16])
     o = O.Oracle(wl, sig, thr, loss, precision="fp64")
     mu = MASS[1] * MO2 / (MASS[1] + MO2)
@@ -318,7 +321,10 @@ def test_associative_detachment_rate_is_distribution_free(T_eV):
         ev, ab, misc = o.counters()
         lam += (n_before - (ab - prev_ab)[:, 1].sum()) * p
         prev_ab = ab
-    assert abs(ev[16] - lam) < 4.5 * math.sqrt(lam), (ev[16], lam)
+    if C == 0.0:
+        assert ev[16] == 0
+    else:
+        assert abs(ev[16] - lam) < 4.5 * math.sqrt(lam), (ev[16], lam)
     assert o.alive(1) == nn - ev[16] - ab[:, 1].sum()
     assert o.alive(0) == ev[16] - ab[:, 0].sum()
 
