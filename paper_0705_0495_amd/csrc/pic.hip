@@ -408,7 +408,7 @@ struct Impl : Base {
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
                   &occ, elds ? (const void*)k_push<R, true> : (const void*)k_push<R, false>, TPB, 0));
     grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
-    grid_scatter = std::max(1, ncu * 4);
+    grid_scatter = std::max(1, ncu * 2);
 
 
     // initial load, deposit, field at t = 0, half step back, first sort
@@ -506,7 +506,7 @@ struct Impl : Base {
 
   int sort() {
     hipLaunchKernelGGL(k_sort_scan<R>, dim3(3), dim3(SCAN_TPB), 0, c->stream, C, D);
-    hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid_scatter), dim3(256), 0, c->stream, C, D);
+    hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid_scatter), dim3(SORT_TPB), 0, c->stream, C, D);
     HIPCHK(c, hipGetLastError());
     for (int s = 0; s < 3; s++) std::swap(D.st[s], D.alt[s]);
     return 0;

@@ -1693,7 +1693,10 @@ __global__ void __launch_bounds__(SCAN_TPB) k_sort_scan_b(const Consts<R>* __res
   k_sort_scan_body<R>(Cs[blockIdx.y], Ds[blockIdx.y]);
 }
 
-constexpr int SORT_TPB = 256;
+// 2048-particle chunks in 512-thread workgroups, two per CU (LDS): the cost
+// of a chunk is mostly its fixed phases (ranks, run reservation, barriers),
+// so larger chunks beat more workgroups of smaller ones
+constexpr int SORT_TPB = 512;
 constexpr int SORT_PER = 4;
 constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
 constexpr int SORT_WIN = 512;  // cells around the middle of a chunk
