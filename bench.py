@@ -21,6 +21,12 @@ itself never touches vy and vz of the ~95 % of particles that do not collide
 (the field is along x); ``achieved_touched``/``frac_touched`` count only the
 32 B (FP32; 48 B in FP64) it must move for every particle.  ``traffic`` is the
 kernel's measured HBM bytes per launch (rocprofv3 counters, profiles/).
+
+Other modes: ``--workload sweep`` (many discharges advanced together),
+``--workload serve`` (the serving loop over a request stream),
+``--workload ablation`` (the metastable pair C = 0 / C = 1/6 on the production
+discharge); ``--coulomb-inter`` adds the unlike-species Coulomb pass to a
+single-discharge run and reports its longest collision chains.
 """
 from __future__ import annotations
 
