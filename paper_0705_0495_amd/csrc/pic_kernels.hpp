@@ -2464,43 +2464,40 @@ __device__ __forceinline__ TaPre<R> ta_pre(const Consts<R>& C, uint4 w) {
   sincos2pi<R>(C, unif<R>(w.z), p.sph, p.cph);
   return p;
 }
+// Every branch of the collision is evaluated and the result selected (the
+// same IEEE operations as ta_pair_m for the case taken): a chain that runs on
+// one lane is bound by instruction latency, and without divergent control
+// flow the square root and reciprocal of u_perp leave its critical path.
+// ok = false (or u = 0) leaves both velocities unchanged.
 template <class R>
-__device__ __forceinline__ void ta_apply(R va[3], R vb[3], R cc, R nrm, R sti, R omci, R cph, R sph, R fa, R fb) {
+__device__ __forceinline__ void ta_apply(bool ok, R va[3], R vb[3], R cc, R nrm, R sti, R omci, R cph, R sph, R fa,
+                                         R fb) {
   const R ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
   const R up2 = ux * ux + uy * uy;
   const R u2 = up2 + uz * uz;
-  if (!(u2 > (R)0)) return;
   const R u = Sqrt(u2);
+  const R up = Sqrt(up2);
+  const R iup = (R)1 / up;
   const R var = cc / (u2 * u);
-  R st, omc;
-  if (var > (R)1) {
-    st = sti;
-    omc = omci;
-  } else {
-    const R d = Sqrt(var) * nrm;
-    const R d2 = d * d;
-    const R inv = (R)1 / ((R)1 + d2);
-    st = (d + d) * inv;
-    omc = (d2 + d2) * inv;
-  }
+  const R d = Sqrt(var) * nrm;
+  const R d2 = d * d;
+  const R inv = (R)1 / ((R)1 + d2);
+  const bool iso = var > (R)1;  // beyond the small-angle model: isotropic
+  const R st = iso ? sti : (d + d) * inv;
+  const R omc = iso ? omci : (d2 + d2) * inv;
   const R s1 = st * cph, s2 = st * sph;
+  const R r = uz * s1, t = u * s2;
+  const bool perp = up2 > (R)0;
   R du[3];
-  if (up2 > (R)0) {
-    const R up = Sqrt(up2);
-    const R iup = (R)1 / up;
-    const R r = uz * s1, t = u * s2;
-    du[0] = (ux * r - uy * t) * iup - ux * omc;
-    du[1] = (uy * r + ux * t) * iup - uy * omc;
-    du[2] = -(up * s1) - uz * omc;
-  } else {
-    du[0] = u * s1;
-    du[1] = u * s2;
-    du[2] = -(u * omc);
-  }
+  du[0] = perp ? (ux * r - uy * t) * iup - ux * omc : u * s1;
+  du[1] = perp ? (uy * r + ux * t) * iup - uy * omc : u * s2;
+  du[2] = perp ? -(up * s1) - uz * omc : -(u * omc);
+  const bool hit = ok && u2 > (R)0;
 #pragma unroll
-  for (int d = 0; d < 3; d++) {
-    va[d] = va[d] + fa * du[d];
-    vb[d] = vb[d] - fb * du[d];
+  for (int k = 0; k < 3; k++) {
+    const R na = va[k] + fa * du[k], nb = vb[k] - fb * du[k];
+    va[k] = hit ? na : va[k];
+    vb[k] = hit ? nb : vb[k];
   }
 }
 
@@ -2622,9 +2619,11 @@ __device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>
           int i = tid >= c0 ? tid : tid + ((c0 - tid + nsml - 1) / nsml) * nsml;
           for (; i < c0 + cn; i += nsml) {
             const int t = i - c0;
-            if (L.c.pos[t] < 0) continue;
+            // slots of a failed rank check collide with nothing (their
+            // velocities are not written back)
             R va[3] = {L.c.vx[t], L.c.vy[t], L.c.vz[t]};
-            ta_apply<R>(va, vb, cf, L.c.nrm[t], L.c.sti[t], L.c.omci[t], L.c.cph[t], L.c.sph[t], fbig, fsml);
+            ta_apply<R>(L.c.pos[t] >= 0, va, vb, cf, L.c.nrm[t], L.c.sti[t], L.c.omci[t], L.c.cph[t], L.c.sph[t],
+                        fbig, fsml);
             L.c.vx[t] = va[0];
             L.c.vy[t] = va[1];
             L.c.vz[t] = va[2];
