@@ -1992,6 +1992,18 @@ __device__ inline void block_scan_excl(int32_t* a, int n, int32_t* wsum) {
 
 __device__ __forceinline__ int coul_bucket(uint32_t h, int nb) { return (int)(((uint64_t)h * (uint32_t)nb) >> 32); }
 
+// Global stores of this workgroup made visible to its other waves before
+// they read them.  The workgroup barrier alone waits only for LDS: each wave
+// first waits for its own vector memory operations (its stores reach the L2),
+// and after the barrier the CU's vector L1 is invalidated so that the reads
+// that follow come from the L2.  (A device-scope fence would also write the
+// L2 back, many times dearer, and is not needed within one workgroup.)
+__device__ __forceinline__ void wg_global_sync() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  asm volatile("buffer_inv sc0" ::: "memory");
+}
+
 // Pairing order of the Coulomb pass: the particles of one (species, cell)
 // segment ordered by (Philox(id, n, 16).x, id).  A counting sort into
 // nb = ceil(m/per) LDS buckets on the hash (monotone in it); a particle's rank
@@ -2030,7 +2042,8 @@ __device__ void coul_rank(const Consts<R>& C, const Store<R>& S, int32_t a, int 
     if (ordp) ordp[r] = (uint16_t)i;
     else ordg[a + r] = a + i;
   }
-  __syncthreads();
+  if (ordg) wg_global_sync();  // other waves read the order from global memory
+  else __syncthreads();
 }
 
 // Collisions of a cell whose velocities are in (vx, vy, vz)[0..m) (LDS or
@@ -2670,7 +2683,7 @@ __device__ __forceinline__ void coul_inter_cell(const Consts<R>& C, const Dev<R>
         st_yz(SS, pb, vb[1], vb[2]);
       }
     }
-    __syncthreads();  // the next pair may take the same particles
+    wg_global_sync();  // the next pair may take the same particles
   }
 }
 

@@ -428,12 +428,12 @@ def _same_state(a, b, label):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_graph_replay_matches_eager(prec):
+def test_graph_replay_matches_eager(prec, inter=False):
     """Captured step sequences (20 steps: sort and Coulomb every 10, twice)
     replayed several times, with eager steps and synchronisation in between,
     give the eager run's state after every chunk; partner reactions boosted so
     that the end-of-step kernel takes both of its paths."""
-    wl = ragged_small(sort_every=10, coulomb_every=10)
+    wl = ragged_small(sort_every=10, coulomb_every=10, coulomb_inter=inter)
     sig, thr, loss = build_tables(partner_boost=3e6)
     ge = _gpu()(wl, sig, thr, loss, precision=prec)
     gg = _gpu()(wl, sig, thr, loss, precision=prec)
@@ -540,3 +540,11 @@ def test_autotune_changes_no_result():
     _same_state(_state(a), _state(b), "after 25 more steps")
     a.close()
     b.close()
+
+
+def test_graph_replay_with_unlike_pass_matches_eager():
+    """The same with the unlike-species Coulomb pass in the captured sequence
+    (its workgroups exchange ranks and velocities through global memory
+    between their phases)."""
+    test_graph_replay_matches_eager("fp32", inter=True)
+
