@@ -440,9 +440,11 @@ def test_graph_replay_matches_eager(prec, inter=False):
     gg.set_graphs(True)
     done = 0
     for k in (20, 20, 13, 27, 40, 5, 60):
+        # one discharge at a time: this compares replay with eager stepping,
+        # not two discharges sharing the GPU
         ge.step(k)
-        gg.step(k)
         ge.sync()
+        gg.step(k)
         gg.sync()
         done += k
         _same_state(_state(ge), _state(gg), f"after {done} steps")
