@@ -43,7 +43,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP = {"fp32": 48, "fp64": 80}      # whole particle state read and written
 BYTES_TOUCHED = {"fp32": 32, "fp64": 48}       # cell, off, vx read and written, id read
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_push.json")
+TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "traffic_k_push.json"),
+                 "fp64": os.path.join(ROOT, "profiles", "traffic_k_push_fp64.json")}
 
 
 def main():
@@ -140,9 +141,10 @@ def main():
     # measured HBM bytes per launch: FETCH_SIZE + WRITE_SIZE counters of the same
     # kernel (calibrated against a copy of known size), scaled to this run's pushes
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    tfile = TRAFFIC_FILES.get(args.precision)
+    if tfile and os.path.exists(tfile):
         try:
-            t = json.load(open(TRAFFIC_FILE))
+            t = json.load(open(tfile))
             if t.get("workload") == args.workload and t.get("precision") == args.precision:
                 traffic = round(t["bytes_per_push"] * psteps / max(launches, 1))
         except (OSError, ValueError, KeyError):
