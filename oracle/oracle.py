@@ -40,7 +40,7 @@ class Params(C.Structure):
         ("pressure_Pa", C.c_double), ("T_gas_K", C.c_double), ("metastable_frac", C.c_double),
         ("eedf_bins", C.c_int32), ("eedf_emax_eV", C.c_double), ("fneg_xbins", C.c_int32),
         ("fneg_ebins", C.c_int32), ("fneg_emax_eV", C.c_double), ("coulomb_every", C.c_int32),
-        ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32),
+        ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32), ("field_off", C.c_int32),
     ]
 
 
@@ -77,6 +77,8 @@ def lib(prec: str = "fp32"):
     L.or_log_enable.argtypes = [C.c_void_p, C.c_int64]
     L.or_scale_velocities.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
     L.or_math.argtypes = [P(C.c_double), C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double)]
+    L.or_load.restype = C.c_int
+    L.or_load.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double), P(C.c_double)]
     L.or_log_read.restype = C.c_int64
     L.or_log_read.argtypes = [C.c_void_p, P(C.c_double), C.c_int64]
     _loaded[prec] = L
@@ -118,7 +120,7 @@ class Oracle:
 
     def __init__(self, wl, sigma, threshold, loss, precision="fp32", drive_dc=False,
                  eedf_bins=128, eedf_emax_eV=64.0, fneg_xbins=32, fneg_ebins=64, fneg_emax_eV=8.0,
-                 coulomb_every=None):
+                 coulomb_every=None, field_off=False):
         self.L = lib(precision)
         self.wl = wl
         p = Params()
@@ -147,6 +149,7 @@ class Oracle:
         p.coulomb_every = wl.coulomb_every if coulomb_every is None else coulomb_every
         p.coulomb_log = wl.coulomb_log
         p.coulomb_inter = 1 if getattr(wl, "coulomb_inter", False) else 0
+        p.field_off = 1 if field_off else 0
         self.params = p
         self.eedf_bins = eedf_bins
         self.nf = fneg_xbins * fneg_ebins
@@ -230,6 +233,18 @@ class Oracle:
     def scale_velocities(self, sp, f):
         a = np.ascontiguousarray(f, dtype=np.float64)
         self.L.or_scale_velocities(self.h, sp, _ptr(a, C.c_double))
+
+    def load(self, parts):
+        """Replace the initial load (test hook, before the first step): parts is
+        a list of three (cell, off, v) arrays, species e, O-, O2+."""
+        n = np.array([len(p[0]) for p in parts], np.int64)
+        cell = np.ascontiguousarray(np.concatenate([p[0] for p in parts]), dtype=np.int32)
+        off = np.ascontiguousarray(np.concatenate([p[1] for p in parts]), dtype=np.float64)
+        v = np.ascontiguousarray(np.concatenate([np.reshape(p[2], (-1, 3)) for p in parts]), dtype=np.float64)
+        rc = self.L.or_load(self.h, _ptr(n, C.c_int64), _ptr(cell, C.c_int32), _ptr(off, C.c_double),
+                            _ptr(v, C.c_double))
+        if rc != 0:
+            raise RuntimeError(f"or_load failed: {rc}")
 
     def log_enable(self, cap):
         self.L.or_log_enable(self.h, cap)

@@ -30,8 +30,8 @@
  *      cells, which also defines the partner populations of the cells.
  *
  * Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter
- * (id_lo, id_hi, n, k), key = 64-bit seed.  Transcendentals of the samplers are
- * evaluated in double and rounded once to `real`.
+ * (id_lo, id_hi, n, k), key = 64-bit seed.  The samplers' sin, cos and ln are
+ * fixed-term series evaluated in `real` (see the elementary functions below).
  */
 #include "pic_oracle.h"
 
@@ -279,7 +279,7 @@ struct or_ctx {
   real Mr_ch[NCH];
   double PG[NCH];        /* tau * n_target for gas channels */
   double PGtot[3];
-  double KP[NCH];        /* tau * M_j / (A dx) for partner channels */
+  double KP[NCH];        /* tau * M_j * W / (A dx) for partner channels */
   double cphi, cE;
   real cc_coul[3], cc_coul_half[3]; /* Eq. (2) prefactor per particle in the cell */
   real cc_inter[3];                  /* the same for the pairs (e, O-), (e, O2+), (O-, O2+) */
@@ -566,7 +566,7 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
       int one[1] = {j};
       c->M_ch[j] = bound_M(sigma, one, 1, mum);
       c->Mr_ch[j] = (real)c->M_ch[j];
-      c->KP[j] = (c->tau[s] * c->M_ch[j]) / (p->area_m2 * c->dx);
+      c->KP[j] = ((c->tau[s] * c->M_ch[j]) * p->weight) / (p->area_m2 * c->dx);
     }
     for (int j = 0; j < NCH; j++) {
       if (partner_of[j] >= 0) continue;
@@ -604,6 +604,7 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
   }
   c->cphi = ((c->dx * QE) * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
   c->cE = (QE * p->weight) / ((EPS0 * 16777216.0) * p->area_m2);
+  if (p->field_off) c->cphi = c->cE = 0.0; /* test switch: the charge does not enter the field */
   int M = p->steps_per_period;
   c->Udrive = (double*)malloc(sizeof(double) * (size_t)M);
   for (int k = 0; k < M; k++) {
@@ -662,6 +663,43 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
   do_sort(c);
   c->step = 0;
   return c;
+}
+
+/* test hook: replace the initial load by the given particles (species in the
+   order e, O-, O2+, n[s] each; ids 0.. in that order) and take the creation
+   steps again: deposit, field at t = 0, half step back, sort.  Only before the
+   first step. */
+int or_load(or_ctx* c, const int64_t n[3], const int32_t* cell, const double* off, const double* v) {
+  if (c->step != 0) return OR_EINVAL;
+  uint64_t id = 0;
+  int64_t k = 0;
+  for (int s = 0; s < 3; s++) {
+    c->st[s].n = 0;
+    if (st_grow(&c->st[s], n[s] + 16)) return OR_ENOMEM;
+    for (int64_t i = 0; i < n[s]; i++, id++, k++) {
+      if (cell[k] < 0 || cell[k] >= c->N || !(off[k] >= 0.0) || !(off[k] < 1.0)) return OR_EINVAL;
+      part q;
+      q.id = id;
+      q.alive = 1;
+      q.cell = cell[k];
+      q.sort_cell = q.cell;
+      q.off = (real)off[k];
+      for (int d = 0; d < 3; d++) q.v[d] = (real)v[3 * k + d];
+      c->st[s].a[c->st[s].n++] = q;
+    }
+  }
+  c->next_id = id;
+  deposit_all(c);
+  solve(c, c->Udrive[0]);
+  for (int s = 0; s < 3; s++)
+    for (int64_t i = 0; i < c->st[s].n; i++) {
+      part* q = &c->st[s].a[i];
+      real Ep = gather(c, q->cell, q->off);
+      real dv = c->hk[s] * Ep;
+      q->v[0] = q->v[0] - dv;
+    }
+  do_sort(c);
+  return OR_OK;
 }
 
 void or_destroy(or_ctx* c) {

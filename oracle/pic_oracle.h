@@ -41,6 +41,8 @@ typedef struct {
   int32_t coulomb_every;      /* intra-species Coulomb collisions every n2 steps, 0 = off */
   double coulomb_log;         /* ln Lambda */
   int32_t coulomb_inter;      /* 1: inter-species Coulomb collisions after the intra-species ones */
+  int32_t field_off;          /* test switch, 1: the particles' charge does not enter the field
+                                 (rate pins at weights whose self field would swamp the step) */
 } or_params;
 
 typedef struct or_ctx or_ctx;
@@ -83,6 +85,9 @@ void or_solve_field(int32_t N, double dx, double cphi, double cE, double U0, con
 void or_math(const double* u, int64_t n, double* sn, double* cs, double* lg);
 /* test hook: multiply velocity component d of every particle of species sp by f[d] */
 void or_scale_velocities(or_ctx* c, int sp, const double f[3]);
+/* test hook: replace the initial load (before the first step) by n[s] particles of each
+   species, concatenated e, O-, O2+: cell, off in [0,1), v (3 per particle) */
+int or_load(or_ctx* c, const int64_t n[3], const int32_t* cell, const double* off, const double* v);
 /* event log: enable with capacity; entries of 16 doubles (see source) */
 void or_log_enable(or_ctx* c, int64_t cap);
 int64_t or_log_read(const or_ctx* c, double* out, int64_t cap);

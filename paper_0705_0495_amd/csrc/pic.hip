@@ -232,7 +232,8 @@ struct Impl : Base {
       C.c2e_g[s] = (R)((2.0 * QE) / mu_g[s]);
     }
     C.vthg = (R)std::sqrt((KB * c->gas.T_gas_K) / MO2);
-    // partner channels 12 (e, O2+), 13 (e, O-), 17 (O-, O2+)
+    // partner channels 12 (e, O2+), 13 (e, O-), 17 (O-, O2+): the slot of Eq. (1)
+    // per partner particle of the cell is tau M_j W / (A dx), W real particles each
     const int pch[3] = {12, 13, 17}, ps[3] = {0, 0, 1}, pt[3] = {2, 1, 2};
     const double* sig = c->sigma.data();
     for (int q = 0; q < 3; q++) {
@@ -245,7 +246,7 @@ struct Impl : Base {
       const int one[1] = {pch[q]};
       const double Mj = bound_sum(sig, one, 1, mu);
       C.Mr_c[q] = (R)Mj;
-      C.KP[q] = (tau[ps[q]] * Mj) / (G.area_m2 * dx);
+      C.KP[q] = ((tau[ps[q]] * Mj) * G.weight) / (G.area_m2 * dx);
     }
     C.ddf = (R)std::sqrt((0.1 * mass[1]) / ME);
     C.adf = (R)std::sqrt(mu_g[1] / ME);

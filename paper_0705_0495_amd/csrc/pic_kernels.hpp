@@ -44,7 +44,7 @@ struct Consts {
   R a_g[3], b_g[3], hmu_g[3], c2e_g[3];
   R vthg;
   R a_c[3], b_c[3], hmu_c[3], c2e_c[3], Mr_c[3];   // partner channels 12, 13, 17
-  double KP[3];
+  double KP[3];        // tau M_j W / (A dx): Eq. (1) slot per partner particle of the cell
   R ddf, adf, hme, hmn;
   R thr[NCH], loss[NCH];
   double PG[NCH];
@@ -229,7 +229,7 @@ __device__ __forceinline__ double Sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float Floor(float x) { return floorf(x); }
 __device__ __forceinline__ double Floor(double x) { return floor(x); }
 
-// samplers: transcendentals in double, rounded once to R
+// samplers: fixed-term series evaluated in R (no library transcendentals)
 // sin and cos of 2 pi u for u in (0,1): u = (k + f)/4 with |f| <= 1/2, Taylor
 // series of sin(pi f/2) and cos(pi f/2) in f with a fixed number of terms in
 // Horner order, then the quadrant k.  ln u for u > 0: u = m 2^e with m in

@@ -15,6 +15,14 @@ AMU = 1.66053906660e-27
 MO2 = 31.998 * AMU
 MASS = (ME, 15.999 * AMU + ME, MO2 - ME)
 
+# The partner reactions (13), (14), (19) are rare with the stand-in cross
+# sections.  Tests of pairing, claims and the partner path of the step's end
+# scale those three channels by this factor: on the small discharge
+# (W = 2210, 10k particles) the partner slots then take about a quarter of the
+# electrons' null-collision bound, about 75 requests and 0.7 accepted partner
+# events per step.
+PARTNER_BOOST = 1.0e5
+
 
 def quiet(wl: Workload, **kw) -> Workload:
     """A workload with (almost) no self field and no Coulomb collisions:

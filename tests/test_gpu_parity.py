@@ -14,6 +14,7 @@ import pytest
 
 from oracle import oracle as O
 from pic_inputs import build_tables, workload
+from tests.oracle_helpers import PARTNER_BOOST
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +76,7 @@ def test_creation_matches_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("boost", [1.0, 3e6])
+@pytest.mark.parametrize("boost", [1.0, PARTNER_BOOST])
 def test_steps_match_oracle(prec, boost):
     wl = ragged_small()
     sig, thr, loss = build_tables(partner_boost=boost)
@@ -98,7 +99,7 @@ def test_steps_match_oracle(prec, boost):
 
 def test_subcycled_ions_match_oracle():
     wl = ragged_small(ion_subcycle=3, sort_every=6, coulomb_every=6)
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     g = _gpu()(wl, sig, thr, loss, precision="fp32")
     o = O.Oracle(wl, sig, thr, loss, precision="fp32")
     for k in range(4):
@@ -131,7 +132,7 @@ def test_one_rf_cycle_diagnostics_match_oracle():
 
 def test_results_independent_of_launch_shape():
     wl = ragged_small()
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     ref = None
     for grid in (0, 1, 7, 61):
         g = _gpu()(wl, sig, thr, loss, precision="fp32")
@@ -217,7 +218,7 @@ def test_coulomb_matches_oracle(prec, lnl):
     ln Lambda = 10 gives small angles only, 1e4 also large angles and the
     isotropic branch; ragged counts give triangles in odd cells."""
     wl = ragged_small(sort_every=5, coulomb_every=5, coulomb_log=lnl)
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     g = _gpu()(wl, sig, thr, loss, precision=prec)
     o = O.Oracle(wl, sig, thr, loss, precision=prec)
     done = 0
@@ -293,7 +294,7 @@ def test_inter_species_coulomb_matches_oracle(prec, lnl):
     ties, and cells where one species is absent; ln Lambda = 1e4 also takes
     the isotropic branch."""
     wl = ragged_small(sort_every=5, coulomb_every=5, coulomb_log=lnl, coulomb_inter=True)
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     g = _gpu()(wl, sig, thr, loss, precision=prec)
     o = O.Oracle(wl, sig, thr, loss, precision=prec)
     done = 0
@@ -434,7 +435,7 @@ def test_graph_replay_matches_eager(prec, inter=False):
     give the eager run's state after every chunk; partner reactions boosted so
     that the end-of-step kernel takes both of its paths."""
     wl = ragged_small(sort_every=10, coulomb_every=10, coulomb_inter=inter)
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     ge = _gpu()(wl, sig, thr, loss, precision=prec)
     gg = _gpu()(wl, sig, thr, loss, precision=prec)
     gg.set_graphs(True)
@@ -530,7 +531,7 @@ def test_autotune_changes_no_result():
     discharge equals a twin stepped the same number of times on the default
     grid, and so does the next stretch on the chosen grid."""
     wl = ragged_small()
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     a = _gpu()(wl, sig, thr, loss, precision="fp32")
     b = _gpu()(wl, sig, thr, loss, precision="fp32")
     g = a.autotune(10)

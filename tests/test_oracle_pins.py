@@ -19,7 +19,8 @@ from scipy.linalg import solve_banded
 from oracle import oracle as O
 from pic_inputs import build_tables, energy_grid
 from pic_inputs import xsec as X
-from tests.oracle_helpers import KB, MASS, ME, MO2, QE, quiet, small, tables_only, zero_tables
+from tests.oracle_helpers import (KB, MASS, ME, MO2, PARTNER_BOOST, QE, quiet, small, tables_only,
+                                  zero_tables)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -365,7 +366,7 @@ def test_maxwell_molecule_relaxation():
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_count_balance_every_step(prec):
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     o = O.Oracle(small(), sig, thr, loss, precision=prec)
     prev_ev, prev_ab, _ = o.counters()
     prev_n = [o.alive(s) for s in range(3)]
@@ -386,7 +387,7 @@ def test_count_balance_every_step(prec):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
 def test_per_event_conservation(prec, tol):
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     o = O.Oracle(small(), sig, thr, loss, precision=prec)
     o.log_enable(400_000)
     o.step(200)
@@ -410,7 +411,7 @@ def test_per_event_conservation(prec, tol):
 
 
 def test_births_get_consecutive_canonical_ids():
-    sig, thr, loss = build_tables(partner_boost=3e6)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     o = O.Oracle(small(), sig, thr, loss, precision="fp32")
     n0 = sum(small().n_init)
     o.step(100)
@@ -460,3 +461,116 @@ def test_sampler_elementary_functions_against_numpy(prec):
     # exact values where the quadrant reduction lands on a node
     s0, c0, l1 = O.math(np.array([0.25, 0.5, 0.75]), prec)
     assert np.allclose(s0, [1, 0, -1], atol=tol_trig) and np.allclose(c0, [0, -1, 0], atol=tol_trig)
+
+
+# ----------------------------------------------------------------------------
+# partner reactions (13), (19), (14): Eq. (1) with the real density
+# n_t = W N_t(c) / (A dx) of the partner species in the test particle's cell
+# ----------------------------------------------------------------------------
+PAIRS = {12: (0, 2), 13: (0, 1), 17: (1, 2)}   # channel: (test species, partner species)
+
+
+@pytest.mark.parametrize("ramp", [False, True])
+@pytest.mark.parametrize("j", [12, 13, 17])
+def test_partner_rates_follow_eq1_with_weight(j, ramp):
+    """One step of Maxwellian loads of the test and partner species, the
+    self field switched off so that a realistic weight W ~ 1e10 can be used,
+    no gas.  The partner channel's cross section is a / sqrt(E) (sigma g = K
+    constant, above the channel's threshold), or that times min(1, E/E1),
+    which makes the thinning by sigma(g) g / M_j reject a good share.
+    Accepted requests per test particle are Poisson with mean
+    tau W N_t(c) / (A dx) <sigma_j g>; a partner taken by several accepted
+    requests goes to one of them, which removes (A_c^2 + A_c)/(2 n_c) of the
+    A_c accepted requests of a cell with n_c partners on average."""
+    s, t = PAIRS[j]
+    n = [0, 0, 0]
+    n[s], n[t] = 100_000, 40_000
+    T = (3.0, 0.8, 0.3)
+    base = small(n_init=tuple(n), T_init_eV=T, n_cells=4, pressure_Pa=0.0, voltage_V=0.0,
+                 coulomb_every=0)
+    sig, thr, loss = build_tables()
+    sig[:] = 0.0
+    E = energy_grid()
+    mu = MASS[s] * MASS[t] / (MASS[s] + MASS[t])
+    kT = mu * (T[s] / MASS[s] + T[t] / MASS[t])       # eV: relative energy is Maxwellian at kT
+    a = 1e-19
+    sig[j] = a / np.sqrt(E)
+    if ramp:
+        sig[j] *= np.minimum(1.0, E / kT)
+    sig[j, E < thr[j]] = 0.0
+    K = a * math.sqrt(2 * QE / mu)
+    kmean = _maxwell_rate(sig[j], thr[j], mu, kT)
+    if not ramp:
+        from scipy.special import gammaincc
+        assert kmean == pytest.approx(K * gammaincc(1.5, thr[j] / kT), rel=1e-6)
+    dt = 1.0 / (base.frequency_Hz * base.steps_per_period)
+    dx = base.gap_m / base.n_cells
+    # free flight of the test particles for one step: their cells when they collide
+    probe = O.Oracle(dataclasses.replace(base, weight=1.0), sig, thr, loss, precision="fp64", field_off=True)
+    ids_s, c_s, f_s, v_s = probe.particles(s)
+    _, c_t, _, _ = probe.particles(t)
+    probe.close()
+    x1 = (c_s + f_s) * dx + v_s[:, 0] * dt
+    c1 = np.floor(x1 / dx).astype(np.int64)
+    c1 = c1[(c1 >= 0) & (c1 < base.n_cells)]
+    n_t = np.bincount(c_t, minlength=base.n_cells).astype(float)
+    n_s = np.bincount(c1, minlength=base.n_cells).astype(float)
+    # W for about 1000 accepted requests
+    W = 1000.0 * base.area_m2 * dx / (dt * kmean * float(np.sum(n_s * n_t)))
+    wl = dataclasses.replace(base, weight=W)
+    o = O.Oracle(wl, sig, thr, loss, precision="fp64", field_off=True)
+    assert o.constants()["pmax_e" if s == 0 else "pmax_n"] < 0.1
+    o.step(1)
+    ev, ab, misc = o.counters()
+    lam_c = n_s * n_t * dt * W * kmean / (base.area_m2 * dx)
+    lam = float(np.sum(lam_c - (lam_c ** 2 + lam_c) / (2.0 * n_t)))
+    assert 800 < lam < 1100
+    assert abs(ev[j] - lam) < 4.5 * math.sqrt(lam), (j, ramp, ev[j], lam)
+    others = [k for k in range(19) if k != j]
+    assert not ev[others].any()
+    # without the weight in the partner density the rate would be W times lower
+    assert W > 1e8
+
+
+# ----------------------------------------------------------------------------
+# ion channels: direct detachment (16) and charge exchange (6) against
+# Maxwellian integrals of the tables, Eq. (1) and (3)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("sp,chans,T_eV", [(1, (14, 15), 3.0), (1, (14, 15), 8.0), (2, (18,), 0.026),
+                                           (2, (18,), 1.0)])
+def test_ion_channel_rates_fp64(sp, chans, T_eV):
+    """Fresh Maxwellian ion load, no field, one step: events of O- elastic (5),
+    direct detachment (16) and O2+ charge exchange (6) (its half momentum
+    transfer value and the bridge of Eq. (3)) are binomial with mean
+    N tau n_gas <sigma_j g>, the average over the relative energy, Maxwellian
+    with kT_eff = mu (kT_s/m_s + kT_g/M)."""
+    n = [0, 0, 0]
+    n[sp] = 300_000
+    T = [3.0, 0.026, 0.026]
+    T[sp] = T_eV
+    wl = quiet(small(n_init=tuple(n), T_init_eV=tuple(T), pressure_Pa=100.0), weight=1e-30)
+    sig, thr, loss = tables_only(chans)
+    dt = 1.0 / (wl.frequency_Hz * wl.steps_per_period)
+    ngas = wl.pressure_Pa / (KB * wl.T_gas_K)
+    mu = MASS[sp] * MO2 / (MASS[sp] + MO2)
+    kT = mu * (T_eV * QE / MASS[sp] + KB * wl.T_gas_K / MO2) / QE
+    # scale a channel up where its rate would give fewer than ~300 events
+    for j in chans:
+        lam = n[sp] * dt * ngas * _maxwell_rate(sig[j], thr[j], mu, kT)
+        if lam < 300:
+            sig[j] *= math.ceil(300 / lam)
+    o = O.Oracle(wl, sig, thr, loss, precision="fp64")
+    assert o.constants()["pmax_n" if sp == 1 else "pmax_p"] < 1.0
+    o.step(1)
+    ev, ab, misc = o.counters()
+    n_mcc = misc["psteps"] - ab[:, sp].sum()
+    checked = 0
+    for j in chans:
+        lam = n_mcc * dt * ngas * _maxwell_rate(sig[j], thr[j], mu, kT)
+        if lam < 30:
+            assert ev[j] < lam + 6 * math.sqrt(lam) + 6, (j, ev[j], lam)
+            continue
+        assert abs(ev[j] - lam) < 4.5 * math.sqrt(lam), (j, ev[j], lam)
+        checked += 1
+    assert checked == len(chans)
+    assert not ev[[k for k in range(19) if k not in chans]].any()
