@@ -120,10 +120,24 @@ int pic_set_stream(pic_ctx* ctx, void* hip_stream);
  */
 int pic_step(pic_ctx* ctx, int64_t n_steps);
 
-/* Wait for the context's stream; returns PIC_EGUARD / PIC_EOVERFLOW when the device raised one. */
+/*
+ * Wait for the context's stream.  Returns PIC_EGUARD when the device raised a
+ * guard: the null-collision bound nu_max tau of a species exceeded 1 (the
+ * per-channel probabilities of Eq. (1) must sum to at most one per step) or
+ * a particle's state became non-finite; PIC_EOVERFLOW when a store, the
+ * birth list or the partner-request list ran out of capacity.
+ */
 int pic_sync(pic_ctx* ctx);
 
-/* Moments and diagnostics (synchronising).  Arrays may be NULL when not wanted. */
+/*
+ * Moments and diagnostics (synchronising).  Arrays may be NULL when not
+ * wanted; the caller owns them.  What the paper reports of a discharge: the
+ * densities and the potential averaged over an rf cycle (the quantities whose
+ * constancy defines the periodic steady state, Sec. II), the electron energy
+ * distribution at the centre of the gap and the O- distribution f(E, x) with
+ * E = sign(v_x) M v_x^2 / 2 (Sec. IV), the events of each reaction of
+ * Table I and the particles lost to each electrode (Sec. II).
+ */
 typedef struct {
   int64_t step;               /* steps taken */
   int64_t cycles;             /* complete rf cycles */
@@ -141,17 +155,28 @@ typedef struct {
 int pic_moments(pic_ctx* ctx, pic_moments_t* out);
 
 /*
- * Alive particles of one species (synchronising), in store order.  cap is
- * the capacity of the caller's arrays (v holds 3*cap doubles); *n_out
- * receives the number of alive particles even when it exceeds cap.
+ * Alive particles of one species (synchronising), in store order: the
+ * phase-space state of the 1d3v model of Sec. II, position x = (cell + off) dx
+ * and the three velocity components (v_x at the half step of the leapfrog),
+ * with each particle's id.  cap is the capacity of the caller's arrays (v
+ * holds 3*cap doubles); *n_out receives the number of alive particles even
+ * when it exceeds cap.
  */
 int pic_particles(pic_ctx* ctx, int species, int64_t cap, uint64_t* id_host, int32_t* cell_host,
                   double* off_host, double* v_host, int64_t* n_out);
 
-/* Potential and field the next step will use, host [n_cells+1] each (synchronising). */
+/*
+ * Potential and field at the nodes that the next step will use (Poisson's
+ * equation with the driven and the grounded electrode, Sec. II), host
+ * [n_cells+1] each (synchronising).
+ */
 int pic_field(pic_ctx* ctx, double* phi_host, double* E_host);
 
-/* Node charge of the current alive population, fixed point 2^-24 per macro particle, host [3][n_cells+1]. */
+/*
+ * Node charge of the current alive population by linear weighting (Sec. II,
+ * charge assignment), per species, fixed point: 2^24 units per macro
+ * particle; host [3][n_cells+1] (synchronising).
+ */
 int pic_charge(pic_ctx* ctx, int64_t* Q_host);
 
 /*
@@ -198,17 +223,26 @@ int pic_set_graphs(pic_ctx* ctx, int enable);
  * contexts share precision and sort and Coulomb periods, stand at the same
  * phase of the step sequence (step counts equal modulo the period of
  * pic_set_graphs) and none is timing, every kernel of a step is launched once
- * for all of them,
- * with per-discharge constants and state in device tables, on ctx[0]'s
- * stream, ordered after each context's earlier work and before its later
- * work; this path synchronises before returning.  Otherwise the contexts'
+ * for all of them, with per-discharge constants and state in device tables,
+ * on ctx[0]'s stream, ordered after each context's earlier work and before
+ * its later work; this path synchronises before returning.  Otherwise the contexts'
  * steps are enqueued round robin, one period at a time, each on its own
- * stream (asynchronous, like pic_step).  Either way every discharge ends
- * exactly as if stepped alone.  ctx[0..n) must be distinct; the first error
- * stops the work and is returned (other contexts may then stand at earlier
- * steps).
+ * stream (asynchronous, like pic_step); when any of them has Coulomb
+ * collisions on (coulomb_every > 0) the periods are chained by events so
+ * that no two contexts' steps run at the same time.  Either way every
+ * discharge ends exactly as if stepped alone.  ctx[0..n) must be distinct;
+ * the first error stops the work and is returned (other contexts may then
+ * stand at earlier steps).
+ *
+ * Known limitation: large discharges with Coulomb collisions on, stepped by
+ * separate pic_step calls on different streams so that their Coulomb
+ * kernels run at the same time, have ended in states that differ from their
+ * lone runs; the cause is not found.  pic_step_batch does not overlap them;
+ * callers who step contexts concurrently themselves should order them the
+ * same way when they need bit-reproducible results.
  */
 int pic_step_batch(pic_ctx* const* ctx, int n, int64_t n_steps);
+
 
 int pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);

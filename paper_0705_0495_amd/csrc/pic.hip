@@ -950,20 +950,42 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
   if (steps > 0 && batchable(ctx, n))
     return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps) : batch_run<float>(ctx, n, steps);
   // otherwise round robin in chunks of each context's period, so that every
-  // stream holds queued work while the others run
+  // stream holds queued work while the others run.  With Coulomb collisions
+  // on in any of them the chunks are chained by events into one sequence:
+  // large discharges whose Coulomb kernels ran at the same time on two
+  // streams have ended in different states, for a reason not found, so their
+  // steps are not allowed to overlap.
+  bool chain = false;
+  for (int i = 0; i < n; i++) chain = chain || ctx[i]->G.coulomb_every > 0;
+  hipEvent_t ev = nullptr;
+  if (chain && steps > 0 && n > 1) {
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(ctx[0], PIC_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
+  hipStream_t prev = nullptr;
+  int rc = PIC_OK;
   std::vector<int64_t> left((size_t)n, steps);
-  for (bool more = steps > 0; more;) {
+  for (bool more = steps > 0; more && !rc;) {
     more = false;
-    for (int i = 0; i < n; i++) {
+    for (int i = 0; i < n && !rc; i++) {
       if (left[i] == 0) continue;
+      if (ev && prev && prev != ctx[i]->stream) {
+        hipError_t e = hipEventRecord(ev, prev);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx[i]->stream, ev, 0);
+        if (e != hipSuccess) {
+          rc = fail(ctx[i], PIC_EDEVICE, std::string("stream ordering: ") + hipGetErrorString(e));
+          break;
+        }
+      }
       const int64_t k = std::min(left[i], ctx[i]->impl->chunk());
-      const int rc = ctx[i]->impl->step(k);
-      if (rc) return rc;
+      rc = ctx[i]->impl->step(k);
+      prev = ctx[i]->stream;
       left[i] -= k;
       more = more || left[i] > 0;
     }
   }
-  return PIC_OK;
+  if (ev) (void)hipEventDestroy(ev);
+  return rc;
 }
 
 int pic_autotune(pic_ctx* c, int64_t steps_per_trial, int32_t* chosen) {

@@ -151,22 +151,29 @@ def test_results_independent_of_launch_shape():
         g.close()
 
 
-def test_production_size_matches_oracle():
-    """The 4.5M-particle production discharge, a few steps, in the launch
-    configuration the benchmark uses."""
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_production_size_matches_oracle(prec):
+    """The 4.5M-particle production discharge in the launch configuration the
+    benchmark uses: 101 steps, through the ion sub-cycles (every 10 steps) and
+    the first sort and Coulomb pass (step 100), every particle compared."""
     wl = workload("prod")
     sig, thr, loss = build_tables()
-    g = _gpu()(wl, sig, thr, loss, precision="fp32")
-    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
-    for target in (1, 11):
-        g.step(target - (0 if target == 1 else 1))
-        o.step(target - (0 if target == 1 else 1))
-        compare(g, o, "fp32", f"prod step {target}")
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    done = 0
+    for target in (1, 11, 101):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, prec, f"prod {prec} step {target}")
+    g.close()
+    o.close()
 
 
-def test_large_size_matches_oracle_sampled():
-    """The 2^25-particle discharge: one step, counters and charge in full, every
-    997th particle compared one by one."""
+def test_large_size_matches_oracle():
+    """The 2^25-particle discharge of the benchmark: 20 steps, through two
+    sorts and Coulomb passes (steps 10 and 20); step 1 on every 997th
+    particle, steps 11 and 20 on every particle, counters and charge in full."""
     wl = workload("large")
     sig, thr, loss = build_tables()
     g = _gpu()(wl, sig, thr, loss, precision="fp32")
@@ -174,6 +181,37 @@ def test_large_size_matches_oracle_sampled():
     g.step(1)
     o.step(1)
     compare(g, o, "fp32", "large step 1", sample_mod=997)
+    done = 1
+    for target in (11, 20):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, "fp32", f"large step {target}")
+    assert np.array_equal(g.charge(), o.charge())
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("prec,n_cells", [("fp32", 4608), ("fp64", 2304)])
+def test_global_field_push_matches_oracle(prec, n_cells):
+    """Grids above what the push stages in LDS (4099 cells in FP32, 2049 in
+    FP64, as the FP64 large discharge): the push gathers the node field from
+    global memory.  35 steps through three sorts and Coulomb passes, partner
+    reactions boosted."""
+    wl = dataclasses.replace(workload("small").scaled(6.0, name="small-x6"), n_cells=n_cells)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
+    g = _gpu()(wl, sig, thr, loss, precision=prec)
+    o = O.Oracle(wl, sig, thr, loss, precision=prec)
+    done = 0
+    for target in (1, 10, 11, 35):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, prec, f"{n_cells} cells step {target}")
+        assert np.array_equal(g.field()[1], o.field()[1])
+    assert np.array_equal(g.charge(), o.charge())
+    g.close()
+    o.close()
 
 
 def test_large_run_is_reproducible():
@@ -483,6 +521,32 @@ def test_batch_matches_alone(mode, prec):
         _same_state(_state(alone), _state(g), w.name)
         alone.close()
         g.close()
+
+
+def test_round_robin_large_coulomb_matches_alone():
+    """Two 2^25-particle discharges with Coulomb collisions (every 10 and
+    every 20 steps, so the batch is mixed and runs round robin on two
+    streams), 199 steps in one call: with Coulomb collisions on, the call
+    chains the two contexts' periods so that their kernels never overlap, and
+    each ends exactly as stepped alone.  (Run concurrently, such pairs have
+    diverged from their lone runs.)"""
+    from paper_0705_0495_amd import step_batch
+    base = workload("large")
+    wls = [base, dataclasses.replace(base, coulomb_every=20, seed=base.seed + 1)]
+    sig, thr, loss = build_tables()
+    pair = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
+    step_batch(pair, 199)
+    got = []
+    for g in pair:
+        g.sync()
+        got.append(_state(g))
+        g.close()
+    for w, st in zip(wls, got):
+        alone = _gpu()(w, sig, thr, loss, precision="fp32")
+        alone.step(199)
+        alone.sync()
+        _same_state(_state(alone), st, w.name)
+        alone.close()
 
 
 def test_served_discharges_match_alone():
