@@ -223,9 +223,11 @@ int pic_set_graphs(pic_ctx* ctx, int enable);
  * contexts share precision and sort and Coulomb periods, stand at the same
  * phase of the step sequence (step counts equal modulo the period of
  * pic_set_graphs) and none is timing, every kernel of a step is launched once
- * for all of them, with per-discharge constants and state in device tables,
- * on ctx[0]'s stream, ordered after each context's earlier work and before
- * its later work; this path synchronises before returning.  Otherwise the contexts'
+ * for all of them, with per-discharge constants and state in device tables
+ * (allocated for ctx[0] at its first batch, kept, and grown when a larger
+ * batch needs more), on ctx[0]'s stream, ordered after each context's
+ * earlier work and before its later work; this path synchronises before
+ * returning.  Otherwise the contexts'
  * steps are enqueued round robin, one period at a time, each on its own
  * stream (asynchronous, like pic_step); when any of them has Coulomb
  * collisions on (coulomb_every > 0) the periods are chained by events so

@@ -80,8 +80,12 @@ struct pic_ctx {
   pic_gas gas;
   std::vector<double> sigma, thr, loss;
   double U_rf, freq, pres;
+  int dev = 0;                   // HIP device of the context's memory
   hipStream_t stream = nullptr;
   hipStream_t own = nullptr;
+  hipEvent_t order_ev = nullptr;  // orders this context's stream before batched launches
+  char* btab = nullptr;           // device tables of batches led by this context (grown, kept)
+  size_t btab_bytes = 0;
   std::string msg;
   int err = 0;
   bool timing = false;
@@ -689,23 +693,30 @@ void split_grid(const std::vector<double>& w, int total, int32_t* off) {
   }
 }
 
-// Steps of n discharges of one precision, same sort and Coulomb periods and
-// same step count, as batched launches (one per kernel for all of them) on
-// ctx[0]'s stream, ordered after every context's earlier work and before its
-// later work.  Synchronising: the tables the launches read are freed at the
-// end.
+// device bytes of the tables of a batch of n discharges: constants, the
+// device state at both parities of the particle buffers, four offset arrays
 template <class R>
-int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
+constexpr size_t batch_table_bytes(int n) {
+  return sizeof(Consts<R>) * (size_t)n + sizeof(Dev<R>) * 2 * (size_t)n + sizeof(int32_t) * 4 * (size_t)(n + 1);
+}
+
+// Steps of n discharges of one precision, same sort and Coulomb periods and
+// same phase, as batched launches (one per kernel for all of them) on
+// ctx[0]'s stream, ordered after every context's earlier work and before its
+// later work.  The launches read their tables from buf (tab_cap bytes of
+// device memory that no other work uses meanwhile).  Synchronising: returns
+// when the steps are done, so that the next call may rewrite the tables.
+template <class R>
+int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_cap) {
   pic_ctx* c0 = ctx[0];
   hipStream_t st = c0->stream;
+  if (batch_table_bytes<R>(n) > tab_cap) return fail(c0, PIC_EINVAL, "batch tables exceed their buffer");
   std::vector<Impl<R>*> im((size_t)n);
   for (int i = 0; i < n; i++) im[i] = static_cast<Impl<R>*>(ctx[i]->impl);
   for (int i = 1; i < n; i++) {
-    hipEvent_t ev;
-    HIPCHK(c0, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HIPCHK(c0, hipEventRecord(ev, ctx[i]->stream));
-    HIPCHK(c0, hipStreamWaitEvent(st, ev, 0));
-    (void)hipEventDestroy(ev);
+    if (ctx[i]->stream == st) continue;
+    HIPCHK(c0, hipEventRecord(ctx[i]->order_ev, ctx[i]->stream));
+    HIPCHK(c0, hipStreamWaitEvent(st, ctx[i]->order_ev, 0));
   }
   // constants, the device state as it is now and with the two particle
   // buffers exchanged (after an odd number of sorts), grid offsets
@@ -735,8 +746,6 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
   off[3 * (n + 1)] = 0;
   for (int i = 0; i < n; i++) off[3 * (n + 1) + i + 1] = (int32_t)(((int64_t)(i + 1) * im[0]->ncu) / n);
   const size_t bc = sizeof(Consts<R>) * n, bd = sizeof(Dev<R>) * 2 * n, bo = sizeof(int32_t) * off.size();
-  char* buf = nullptr;
-  HIPCHK(c0, hipMalloc(&buf, bc + bd + bo));
   HIPCHK(c0, hipMemcpyAsync(buf, hc.data(), bc, hipMemcpyHostToDevice, st));
   HIPCHK(c0, hipMemcpyAsync(buf + bc, hd.data(), bd, hipMemcpyHostToDevice, st));
   HIPCHK(c0, hipMemcpyAsync(buf + bc + bd, off.data(), bo, hipMemcpyHostToDevice, st));
@@ -779,16 +788,16 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps) {
       for (int s = 0; s < 3; s++) std::swap(im[i]->D.st[s], im[i]->D.alt[s]);
   }
   const hipError_t es = hipStreamSynchronize(st);
-  (void)hipFree(buf);
   if (rc) return rc;
   if (es != hipSuccess) return fail(c0, PIC_EDEVICE, std::string("batch: ") + hipGetErrorString(es));
   return 0;
 }
 
-// the batched path applies when every context has the same precision,
-// periods and step count, no timing and no replacement stream shared
-bool batchable(pic_ctx* const* ctx, int n) {
-  if (n < 2 || n > BATCH_MAX) return false;
+// the batched launches apply when every context has the same precision and
+// periods, stands at the same phase of the step sequence, lives on the same
+// device and is not timing
+bool batch_compatible(pic_ctx* const* ctx, int n) {
+  if (n < 1 || n > BATCH_MAX) return false;
   const pic_geometry& G0 = ctx[0]->G;
   for (int i = 0; i < n; i++) {
     const pic_geometry& G = ctx[i]->G;
@@ -798,11 +807,34 @@ bool batchable(pic_ctx* const* ctx, int n) {
     // stand at the same phase of it (the steps themselves may differ)
     const int64_t P = ctx[0]->impl->chunk_period();
     if (ctx[i]->timing || ctx[i]->impl->steps_done() % P != ctx[0]->impl->steps_done() % P) return false;
+    if (ctx[i]->dev != ctx[0]->dev) return false;
     for (int j = 0; j < i; j++)
       if (ctx[j] == ctx[i]) return false;
   }
   return true;
 }
+
+// more than one discharge: one launch per kernel pays off
+bool batchable(pic_ctx* const* ctx, int n) { return n >= 2 && batch_compatible(ctx, n); }
+
+// the resident table buffer of the batches led by c, grown to at least bytes
+int batch_tables(pic_ctx* c, size_t bytes, char** out) {
+  if (c->btab_bytes < bytes) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->btab) (void)hipFree(c->btab);
+    c->btab = nullptr;
+    c->btab_bytes = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 2, 64 * 1024);
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return fail(c, PIC_ENOMEM, "hipMalloc of the batch tables failed");
+    c->btab = (char*)p;
+    c->btab_bytes = want;
+  }
+  *out = c->btab;
+  return 0;
+}
+
 
 }  // namespace
 
@@ -842,8 +874,15 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       delete c;
       return PIC_EINVAL;
     }
-  hipError_t e = hipStreamCreate(&c->own);
+  hipError_t e = hipGetDevice(&c->dev);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
+    delete c;
+    return PIC_EDEVICE;
+  }
+  e = hipStreamCreate(&c->own);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(c->order_ev);
     delete c;
     return PIC_EDEVICE;
   }
@@ -854,6 +893,7 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
   if (rc) {
     delete c->impl;
     (void)hipStreamDestroy(c->own);
+    (void)hipEventDestroy(c->order_ev);
     delete c;
     return rc;
   }
@@ -947,8 +987,15 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
     if (!ctx[i]) return PIC_EINVAL;
     if (ctx[i]->err) return ctx[i]->err;
   }
-  if (steps > 0 && batchable(ctx, n))
-    return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps) : batch_run<float>(ctx, n, steps);
+  if (steps > 0 && batchable(ctx, n)) {
+    const bool f64 = ctx[0]->G.precision == PIC_FP64;
+    const size_t bytes = f64 ? batch_table_bytes<double>(n) : batch_table_bytes<float>(n);
+    char* buf = nullptr;
+    const int rc = batch_tables(ctx[0], bytes, &buf);
+    if (rc) return rc;
+    return f64 ? batch_run<double>(ctx, n, steps, buf, ctx[0]->btab_bytes)
+               : batch_run<float>(ctx, n, steps, buf, ctx[0]->btab_bytes);
+  }
   // otherwise round robin in chunks of each context's period, so that every
   // stream holds queued work while the others run.  With Coulomb collisions
   // on in any of them the chunks are chained by events into one sequence:
@@ -1003,6 +1050,8 @@ int pic_set_grid(pic_ctx* c, int32_t g) {
 int pic_destroy(pic_ctx* c) {
   if (!c) return PIC_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  if (c->btab) (void)hipFree(c->btab);
+  if (c->order_ev) (void)hipEventDestroy(c->order_ev);
   delete c->impl;
   for (auto& p : c->events) {
     (void)hipEventDestroy(p.first);
