@@ -15,7 +15,8 @@
  *
  * Conventions
  *   - Every function returns 0 (PIC_OK) or a negative PIC_E* code.  Errors are
- *     sticky per context; pic_last_error() returns a message.
+ *     sticky per context (except the argument checks that say otherwise);
+ *     pic_last_error() returns the message of the last one.
  *   - Pointers named *_host are host memory owned by the caller; the library
  *     never keeps them after the call returns and never frees them.  All device
  *     memory is allocated and freed by the library.
@@ -245,6 +246,23 @@ int pic_set_graphs(pic_ctx* ctx, int enable);
  */
 int pic_step_batch(pic_ctx* const* ctx, int n, int64_t n_steps);
 
+/*
+ * For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc and hipFree while they run): the batched
+ * launches of pic_step_batch, with the batch's tables (constants, device
+ * state and grid offsets of each discharge) in a fixed device array of the
+ * library instead of memory allocated for the leading context.  The call
+ * allocates nothing.  Limits: 1 <= n <= PIC_BATCH_STATIC_MAX discharges that
+ * share precision, sort and Coulomb periods, the phase of the step sequence
+ * and the device, none timing; otherwise PIC_EINVAL with a message in
+ * pic_last_error(ctx[0]), no work done and the contexts still usable (the
+ * error is not sticky).  Synchronising, like the batched
+ * path of pic_step_batch; results are identical to it.  Every call on a GPU
+ * uses that GPU's one array: calls from several host threads that overlap
+ * on one GPU race and must not be made.
+ */
+#define PIC_BATCH_STATIC_MAX 64
+int pic_step_batch_static(pic_ctx* const* ctx, int n, int64_t n_steps);
 
 int pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);

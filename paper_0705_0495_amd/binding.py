@@ -80,6 +80,7 @@ def lib():
     L.pic_set_graphs.argtypes = [C.c_void_p, C.c_int]
     L.pic_autotune.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
     L.pic_step_batch.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
+    L.pic_step_batch_static.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
     L.pic_destroy.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]
     L.pic_last_error.restype = C.c_char_p
@@ -238,3 +239,17 @@ def step_batch(discharges, n_steps):
             if msg:
                 raise PicError(rc, msg.decode())
         raise PicError(rc, "")
+
+
+def step_batch_static(discharges, n_steps):
+    """Batched steps without library allocations (pic_step_batch_static): the
+    batch's tables live in a fixed device array; at most PIC_BATCH_STATIC_MAX
+    (64) discharges of the same precision, periods and phase."""
+    if not discharges:
+        return
+    L = discharges[0].L
+    arr = (C.c_void_p * len(discharges))(*[d.h for d in discharges])
+    rc = L.pic_step_batch_static(arr, len(discharges), n_steps)
+    if rc != 0:
+        msg = L.pic_last_error(discharges[0].h)
+        raise PicError(rc, msg.decode() if msg else "")

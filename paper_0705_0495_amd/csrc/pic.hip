@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,6 +105,12 @@ static int fail(pic_ctx* c, int code, const std::string& m) {
     }
   }
   return code;
+}
+
+// an argument error that leaves the context usable: message only, not sticky
+static int reject(pic_ctx* c, const std::string& m) {
+  if (c && !c->err) c->msg = m;
+  return PIC_EINVAL;
 }
 
 #define HIPCHK(ctx, call)                                                                     \
@@ -835,6 +842,34 @@ int batch_tables(pic_ctx* c, size_t bytes, char** out) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Tables of pic_step_batch_static: a fixed device array instead of library
+// allocations.  In host code `scratch` names a host-side stand-in; its device
+// address on each GPU comes from hipGetSymbolAddress, taken once per device
+// when the first context is created there, and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = std::max(batch_table_bytes<float>(PIC_BATCH_STATIC_MAX),
+                                          batch_table_bytes<double>(PIC_BATCH_STATIC_MAX));
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+std::mutex scratch_mu;
+std::vector<char*> scratch_dev;  // device address of scratch per HIP device (null: not taken yet)
+
+// with device dev current
+hipError_t scratch_setup(int dev) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if ((int)scratch_dev.size() <= dev) scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (scratch_dev[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) scratch_dev[dev] = (char*)p;
+  return e;
+}
+
+char* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return dev < (int)scratch_dev.size() ? scratch_dev[dev] : nullptr;
+}
 
 }  // namespace
 
@@ -875,6 +910,7 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       return PIC_EINVAL;
     }
   hipError_t e = hipGetDevice(&c->dev);
+  if (e == hipSuccess) e = scratch_setup(c->dev);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete c;
@@ -1035,6 +1071,26 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
   return rc;
 }
 
+int pic_step_batch_static(pic_ctx* const* ctx, int n, int64_t steps) {
+  if (!ctx || n < 1 || steps < 0) return PIC_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!ctx[i]) return PIC_EINVAL;
+    if (ctx[i]->err) return ctx[i]->err;
+  }
+  if (n > PIC_BATCH_STATIC_MAX)
+    return reject(ctx[0], "pic_step_batch_static: " + std::to_string(n) + " discharges, at most " +
+                              std::to_string(PIC_BATCH_STATIC_MAX));
+  if (!batch_compatible(ctx, n))
+    return reject(ctx[0],
+                  "pic_step_batch_static: the discharges differ in precision, periods, phase or device, repeat, "
+                  "or one is timing");
+  if (steps == 0) return PIC_OK;
+  char* buf = scratch_of(ctx[0]->dev);
+  if (!buf) return fail(ctx[0], PIC_EDEVICE, "pic_step_batch_static: no device address of the static tables");
+  return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps, buf, SCRATCH_BYTES)
+                                         : batch_run<float>(ctx, n, steps, buf, SCRATCH_BYTES);
+}
+
 int pic_autotune(pic_ctx* c, int64_t steps_per_trial, int32_t* chosen) {
   if (!c || steps_per_trial <= 0) return PIC_EINVAL;
   if (c->err) return c->err;
@@ -1064,7 +1120,7 @@ int pic_destroy(pic_ctx* c) {
 
 const char* pic_last_error(const pic_ctx* c) {
   if (!c) return "null context";
-  return c->err ? c->msg.c_str() : "";
+  return c->msg.c_str();
 }
 
 }  // extern "C"
