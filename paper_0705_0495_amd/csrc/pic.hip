@@ -132,6 +132,11 @@ struct Impl : Base {
   int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, ncu = 1;
   int64_t nstep = 0;  // steps enqueued
   bool elds = false;  // k_push stages the node field in LDS
+  Dev<R> hD[2];             // host source of the device copies (kept until the copies are done)
+  Consts<R>* dC = nullptr;  // device copies of C and of D at both buffer parities (read by k_push)
+  Dev<R>* dD = nullptr;
+  const int32_t* dev_parity0_cell = nullptr;  // D.st[0].cell at parity 0
+  int tab_total = 0;  // values of the compact gas-channel copies (Dev::sigc)
   bool graphs = false;                // replay captured step sequences
   hipGraphExec_t gexec = nullptr;     // period() steps from a step count divisible by period()
 
@@ -278,6 +283,30 @@ struct Impl : Base {
     const double Mn = bound_sum(sig, gn, 2, mu_g[1]);
     const double Mp = bound_sum(sig, gp, 1, mu_g[2]);
     const double Mad = bound_sum(sig, gad, 1, mu_g[1]);
+    // compact copies of each species' gas channels for the collisions' LDS:
+    // channel j from node tab_k0[j] (the last zero node below its first
+    // nonzero one) up; species s's copy at tab_base[s] of Dev::sigc
+    {
+      const int g0[3] = {0, 14, 18}, gn[3] = {12, 3, 1};
+      for (int j = 0; j < NCH; j++) C.tab_k0[j] = C.tab_off[j] = 0;
+      int base = 0;
+      for (int s = 0; s < 3; s++) {
+        int off = 0;
+        for (int j = g0[s]; j < g0[s] + gn[s]; j++) {
+          int f = 0;
+          while (f < NPT && sig[(size_t)j * NPT + f] == 0.0) f++;
+          const int k0 = f >= NPT ? NPT : std::max(f - 1, 0);
+          C.tab_k0[j] = k0;
+          C.tab_off[j] = off;
+          off += NPT - k0;
+        }
+        const int padded = (off + 3) & ~3;
+        C.tab_n[s] = (size_t)padded * sizeof(R) <= (size_t)TAB_LDS_BYTES ? off : 0;
+        C.tab_base[s] = base;
+        base += padded;
+      }
+      tab_total = base;
+    }
     C.PGtot[0] = C.PG[0] * Me;
     C.PGtot[1] = C.PG[14] * Mn + C.PG[16] * Mad;
     C.PGtot[2] = C.PG[18] * Mp;
@@ -406,12 +435,37 @@ struct Impl : Base {
       for (int k = 0; k < NPT; k++) tab[(size_t)k * TS + j] = (R)c->sigma[(size_t)j * NPT + k];
     HIPCHK(c, hipMemcpyAsync(Ud, U.data(), sizeof(double) * U.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(sg, tab.data(), sizeof(R) * tab.size(), hipMemcpyHostToDevice, c->stream));
+    // (host buffers of the asynchronous copies live until the synchronisation at the end)
+    std::vector<R> cmp((size_t)std::max(tab_total, 4), (R)0);
+    {
+      const int g0[3] = {0, 14, 18}, gn[3] = {12, 3, 1};
+      for (int s = 0; s < 3; s++)
+        for (int j = g0[s]; j < g0[s] + gn[s]; j++)
+          for (int k = C.tab_k0[j]; k < NPT; k++)
+            cmp[(size_t)C.tab_base[s] + C.tab_off[j] + (k - C.tab_k0[j])] = (R)c->sigma[(size_t)j * NPT + k];
+      R* sc;
+      if ((rc = alloc(&sc, cmp.size()))) return rc;
+      D.sigc = sc;
+      HIPCHK(c, hipMemcpyAsync(sc, cmp.data(), sizeof(R) * cmp.size(), hipMemcpyHostToDevice, c->stream));
+    }
     Counters h;
     memset(&h, 0, sizeof(h));
     h.next_id = G.n_init[0] + G.n_init[1] + G.n_init[2];
     HIPCHK(c, hipMemcpyAsync(D.ctr, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(D.N, G.n_init, sizeof(int64_t) * 3, hipMemcpyHostToDevice, c->stream));
 
+    // the kernel constants and the device state at both buffer parities, for
+    // the kernels that read them from device memory
+    {
+      if ((rc = alloc(&dC, 1))) return rc;
+      if ((rc = alloc(&dD, 2))) return rc;
+      dev_parity0_cell = D.st[0].cell;
+      hD[0] = D;
+      hD[1] = D;
+      for (int s = 0; s < 3; s++) std::swap(hD[1].st[s], hD[1].alt[s]);
+      HIPCHK(c, hipMemcpyAsync(dC, &C, sizeof(C), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(dD, hD, sizeof(hD), hipMemcpyHostToDevice, c->stream));
+    }
     // launch shapes
     int dev = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
@@ -540,8 +594,9 @@ struct Impl : Base {
         c->ev_used++;
         HIPCHK(c, hipEventRecord(e0, c->stream));
       }
-      if (elds) hipLaunchKernelGGL((k_push<R, true>), dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
-      else hipLaunchKernelGGL((k_push<R, false>), dim3(grid_push), dim3(TPB), 0, c->stream, C, D);
+      const Dev<R>* dpar = dD + (D.st[0].cell == dev_parity0_cell ? 0 : 1);
+      if (elds) hipLaunchKernelGGL((k_push<R, true>), dim3(grid_push), dim3(TPB), 0, c->stream, dC, dpar);
+      else hipLaunchKernelGGL((k_push<R, false>), dim3(grid_push), dim3(TPB), 0, c->stream, dC, dpar);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
       HIPCHK(c, hipGetLastError());
       nstep++;

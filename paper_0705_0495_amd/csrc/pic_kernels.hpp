@@ -55,6 +55,11 @@ struct Consts {
   R ccoul[3], ccoul_h[3];   // Eq. (2) prefactor per particle in the cell: full and half interval
   R cinter[3], finter[3][2];  // unlike pairs (e,O-), (e,O2+), (O-,O2+): Eq. (2) with the reduced mass, mu/m_a, mu/m_b
   R sinc[10], cosc[11], logc[12], ln2, sqrt2;  // series of the samplers' elementary functions
+  // compact copy of each species' gas channels for LDS: channel j keeps nodes
+  // [tab_k0[j], NPT) (the nodes below are zero) at tab_off[j]; tab_n[s]
+  // values for species s, 0 when they do not fit (then read from global)
+  int32_t tab_k0[NCH], tab_off[NCH], tab_n[3];
+  int32_t tab_base[3];  // where species s's compact copy starts in Dev::sigc (a multiple of 4)
 };
 
 // terms of the elementary-function series per precision
@@ -158,6 +163,7 @@ struct Dev {
   double* E;        // [Nc+1]
   const double* U;  // [M]
   const R* sig;     // [NPT][TS]
+  const R* sigc;    // compact gas-channel copies per species (Consts::tab_*), staged into LDS
   Birth<R>* nb;
   int32_t nb_cap, req_cap;
   int32_t* nbc;     // [4] total, per species
@@ -339,12 +345,13 @@ __device__ __forceinline__ Lookup<double> lookup(double E) {
   return {(int)((b >> 47) - (0x3F10000000000000ull >> 47)), (double)(b & ((1ull << 47) - 1)) * 0x1p-47, 0};
 }
 
+// sigma of column j of a table with rows of `stride` values per node
 template <class R>
-__device__ __forceinline__ R sig_at(const R* tab, int j, const Lookup<R>& L) {
-  if (L.mode == 2) return tab[(NPT - 1) * TS + j];
-  R s0 = tab[L.k * TS + j];
+__device__ __forceinline__ R sig_at(const R* tab, int stride, int j, const Lookup<R>& L) {
+  if (L.mode == 2) return tab[(NPT - 1) * stride + j];
+  R s0 = tab[L.k * stride + j];
   if (L.mode == 1) return s0;
-  R s1 = tab[(L.k + 1) * TS + j];
+  R s1 = tab[(L.k + 1) * stride + j];
   R d = s1 - s0;
   R p = L.t * d;
   return s0 + p;
@@ -374,6 +381,18 @@ __device__ inline double i128_to_double(__int128 x) {
     d = ldexp(u64_to_double_rn(t), sh);
   }
   return neg ? -d : d;
+}
+
+// Global stores of this workgroup made visible to its other waves before
+// they read them.  The workgroup barrier alone waits only for LDS: each wave
+// first waits for its own vector memory operations (its stores reach the L2),
+// and after the barrier the CU's vector L1 is invalidated so that the reads
+// that follow come from the L2.  (A device-scope fence would also write the
+// L2 back, many times dearer, and is not needed within one workgroup.)
+__device__ __forceinline__ void wg_global_sync() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  asm volatile("buffer_inv sc0" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -771,30 +790,85 @@ __device__ __forceinline__ bool gas_event(const Consts<R>& C, const Dev<R>& D, i
   return true;
 }
 
+// gas channels of species S: first channel and count (decision order)
+template <int S> struct GasCh {
+  static constexpr int G0 = (S == 0) ? 0 : (S == 1 ? 14 : 18);
+  static constexpr int NG = (S == 0) ? 12 : (S == 1 ? 3 : 1);
+};
+
+// the cross sections the decision reads: the compact LDS copy of the
+// species' gas channels (lds) or the full table in global memory
+template <class R>
+struct TabRef {
+  const R* p;
+  bool lds;
+};
+
+// sigma of channel j from the compact copy: nodes below tab_k0[j] are zero
+template <class R>
+__device__ __forceinline__ R sig_compact(const Consts<R>& C, const R* tab, int j, const Lookup<R>& L) {
+  const int k0 = C.tab_k0[j];
+  const R* t = tab + C.tab_off[j] - k0;
+  if (L.mode == 2) return (NPT - 1 >= k0) ? t[NPT - 1] : (R)0;
+  if (L.k < k0) return (R)0;
+  R s0 = t[L.k];
+  if (L.mode == 1) return s0;
+  R s1 = t[L.k + 1];
+  R d = s1 - s0;
+  R p = L.t * d;
+  return s0 + p;
+}
+
+template <class R>
+__device__ __forceinline__ R sig_of(const Consts<R>& C, const TabRef<R>& T, int j, const Lookup<R>& L) {
+  return T.lds ? sig_compact(C, T.p, j, L) : sig_at(T.p, TS, j, L);
+}
+
+// what a candidate's collision reads besides its record: (vy, vz) of its
+// slot and the partner populations of its cell (segment lengths of the
+// last sort), loaded for several candidates before any of them is collided
+template <class R>
+struct CandIn {
+  Cand<R> k;
+  R vy, vz;
+  int32_t Lc[2];
+};
+
 template <class R, int S>
-__device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D, DiagLds& G, int64_t r, uint32_t n) {
+__device__ __forceinline__ void cand_partners(const Consts<R>& C, const Dev<R>& D, CandIn<R>& a) {
+  const int N = C.N;
+  constexpr int NP = (S == 0) ? 2 : (S == 1 ? 1 : 0);
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    const int chan = (S == 0) ? 12 + q : 17;
+    const int t = (chan == 13) ? 1 : 2;
+    a.Lc[q] = D.seg[t * (N + 1) + a.k.cell + 1] - D.seg[t * (N + 1) + a.k.cell];
+  }
+}
+
+template <class R, int S>
+__device__ __forceinline__ void collide_apply(const Consts<R>& C, const Dev<R>& D, DiagLds& G, const TabRef<R>& T,
+                                              const CandIn<R>& a, uint32_t n) {
   const Store<R> st = D.st[S];
   const int N = C.N;
-  const Cand<R> k = D.cand[S][r];
-  const int slot = k.slot;
-  const int cell = k.cell;
-  const R off = k.off;
+  const int slot = a.k.slot;
+  const int cell = a.k.cell;
+  const R off = a.k.off;
   R v[3];
-  v[0] = k.vx;
-  ld_yz(st, slot, v[1], v[2]);
-  const uint64_t id = k.id;
+  v[0] = a.k.vx;
+  v[1] = a.vy;
+  v[2] = a.vz;
+  const uint64_t id = a.k.id;
   const uint4 w = rng(C, id, n, 0);
   const double U = unif52(w.x, w.y);
   double cum = 0.0;
-  // partner channels first: slot size tau n_t(c) M_j (thinned in k_tail)
+  // partner channels first: slot size tau n_t(c) M_j (thinned at the step's end)
   constexpr int NP = (S == 0) ? 2 : (S == 1 ? 1 : 0);
 #pragma unroll
   for (int q = 0; q < NP; q++) {
     const int pi = (S == 0) ? q : 2;
     const int chan = (S == 0) ? 12 + q : 17;
-    const int t = (chan == 13) ? 1 : 2;
-    const int32_t Lc = D.seg[t * (N + 1) + cell + 1] - D.seg[t * (N + 1) + cell];
-    cum = cum + (double)Lc * C.KP[pi];
+    cum = cum + (double)a.Lc[q] * C.KP[pi];
     if (U < cum) {
       const int r = atomicAdd(D.nreq, 1);
       if (r < D.req_cap) {
@@ -829,14 +903,13 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
   const R Erel = C.hmu_g[S] * g2;
   if (Erel >= (R)16384) atomicAdd(&G.tophits, 1);
   const Lookup<R> Lk = lookup(Erel);
-  constexpr int G0 = (S == 0) ? 0 : (S == 1 ? 14 : 18);
-  constexpr int NG = (S == 0) ? 12 : (S == 1 ? 3 : 1);
+  constexpr int G0 = GasCh<S>::G0, NG = GasCh<S>::NG;
   int hit = -1;
 #pragma unroll
   for (int q = 0; q < NG; q++) {
     const int j = G0 + q;
     R sg = 0;
-    if (Erel >= C.thr[j]) sg = sig_at(D.sig, j, Lk) * g;
+    if (Erel >= C.thr[j]) sg = sig_of(C, T, j, Lk) * g;
     cum = cum + C.PG[j] * (double)sg;
     if (hit < 0 && U < cum) hit = j;
   }
@@ -854,20 +927,65 @@ __device__ __forceinline__ void collide_one(const Consts<R>& C, const Dev<R>& D,
   diag_alive<R, S>(C, G, cell, v[0], v[1], v[2]);
 }
 
+// The collisions of candidates e = tid, tid + TPB, ... < tot of a batch (rec(e):
+// record index), two per round and thread: both records, then both
+// candidates' other inputs are loaded before either is collided, so that each
+// dependent load is waited for once per pair.
+template <class R, int S, class Rec>
+__device__ __forceinline__ void collide_range(const Consts<R>& C, const Dev<R>& D, DiagLds& G, const TabRef<R>& T,
+                                              int tot, Rec rec, uint32_t n) {
+  const Store<R> st = D.st[S];
+  for (int e = threadIdx.x; e < tot; e += 2 * TPB) {
+    const bool two = e + TPB < tot;
+    CandIn<R> a, b;
+    a.k = D.cand[S][rec(e)];
+    if (two) b.k = D.cand[S][rec(e + TPB)];
+    ld_yz(st, a.k.slot, a.vy, a.vz);
+    cand_partners<R, S>(C, D, a);
+    if (two) {
+      ld_yz(st, b.k.slot, b.vy, b.vz);
+      cand_partners<R, S>(C, D, b);
+    }
+    collide_apply<R, S>(C, D, G, T, a, n);
+    if (two) collide_apply<R, S>(C, D, G, T, b, n);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fused particle step: gather, leapfrog, absorption, null-collision test,
 // deposit; then the collisions of the workgroup's own candidates
 // ---------------------------------------------------------------------------
-template <class R>
-struct PushLds {
-  uint64_t win[2][WIN];  // deposit windows of consecutive tiles (alternating)
-  DiagLds G;
-};
-
 // node field staged in LDS by k_push when the grid is small enough (16 KB)
 constexpr int PUSH_ELDS_BYTES = 16 * 1024 + 16;
 template <class R> struct PushE {
   static constexpr int MAXN = PUSH_ELDS_BYTES / (int)sizeof(R) - 1;  // cells
+};
+
+// LDS bytes for the cross sections of one species during its collisions:
+// the same bytes as the push phase's deposit windows and node field, so that
+// the kernel's LDS (34 KB) still lets four workgroups share a CU.  The
+// electrons' twelve gas channels in full would take 43 KB, which leaves room
+// for two; stored from the first nonzero node of each channel up they take
+// 22 KB in FP32.
+constexpr int TAB_LDS_BYTES = 24576;
+constexpr int FB = 64;  // tiles per collision batch (a species' tiles of one workgroup in the large discharge)
+
+// LDS of the fused particle kernel.  The push phase uses the two deposit
+// windows of consecutive tiles (alternating) and, with ELDS, the node field;
+// the collision phase reuses the same bytes for the compact cross sections of
+// the gas channels of the species it collides
+template <class R, bool ELDS>
+struct PushLds {
+  union __attribute__((aligned(16))) {
+    struct {
+      uint64_t win[2][WIN];
+      R El[ELDS ? PushE<R>::MAXN + 1 : 1];
+    } p;
+    R tab[TAB_LDS_BYTES / sizeof(R)];
+  } u;
+  DiagLds G;
+  int32_t cpre[FB * 4 + 1];
+  int32_t wsum[TPB / 64];
 };
 
 template <class R> struct Vec4;
@@ -903,6 +1021,39 @@ __device__ __forceinline__ void deposit_win(uint64_t* win, int32_t* cnt, int64_t
   }
 }
 
+// one thread's PPT consecutive particles of a tile (16-byte vector loads)
+template <class R>
+struct TileRegs {
+  int32_t c[PPT];
+  R off[PPT], vx[PPT];
+  uint64_t id[PPT];
+};
+
+template <class R>
+__device__ __forceinline__ void load_tile(const Store<R>& st, int64_t t0, int64_t Ns, TileRegs<R>& P) {
+  const int64_t s0 = t0 + (int64_t)PPT * threadIdx.x;
+  if (s0 + PPT - 1 < Ns) {
+#pragma unroll
+    for (int h = 0; h < PPT; h += 4) {
+      const int4 cv = *(const int4*)(st.cell + s0 + h);
+      P.c[h] = cv.x; P.c[h + 1] = cv.y; P.c[h + 2] = cv.z; P.c[h + 3] = cv.w;
+      Vec4<R>::load(st.off + s0 + h, P.off + h);
+      Vec4<R>::load(st.vx + s0 + h, P.vx + h);
+      const ulonglong2 ia = *(const ulonglong2*)(st.id + s0 + h), ib = *(const ulonglong2*)(st.id + s0 + h + 2);
+      P.id[h] = ia.x; P.id[h + 1] = ia.y; P.id[h + 2] = ib.x; P.id[h + 3] = ib.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; q++) {
+      const bool in = s0 + q < Ns;
+      P.c[q] = in ? st.cell[s0 + q] : DEAD;
+      P.off[q] = in ? st.off[s0 + q] : (R)0;
+      P.vx[q] = in ? st.vx[s0 + q] : (R)0;
+      P.id[q] = in ? st.id[s0 + q] : 0;
+    }
+  }
+}
+
 struct TileCount {
   int pushed, abs0, abs1;
   int32_t next_cell;  // first cell of the workgroup's next tile, read before this tile's barrier
@@ -922,9 +1073,10 @@ __device__ __forceinline__ int win_base(int32_t first_cell) { return (first_cell
 // own region of the list.  next_first points at the first cell of the
 // workgroup's next tile (null if none).
 template <class R, int S, bool ELDS>
-__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, PushLds<R>& L, const R* El,
-                                               int buf, int64_t t0, int64_t Ns, uint32_t n, uint64_t T0,
-                                               double pmax, int base, const int32_t* next_first) {
+__device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, uint64_t* win, DiagLds& G,
+                                               const R* El, const TileRegs<R>& P, int64_t t0, int64_t Ns,
+                                               uint32_t n, uint64_t T0, double pmax, int base,
+                                               const int32_t* next_first) {
   TileCount tc = {0, 0, 0, DEAD};
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -932,33 +1084,19 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
   const Store<R> st = D.st[S];
   int32_t* cnt_s = D.cnt + (size_t)S * N;
   int64_t* F_s = D.F + (size_t)S * N;
-  uint64_t* win = L.win[buf];
   if (next_first) tc.next_cell = *next_first;
   const int64_t s0 = t0 + (int64_t)PPT * tid;
   int32_t c[PPT];
   R off[PPT], vx[PPT];
   uint64_t id[PPT];
-  const bool full = s0 + PPT - 1 < Ns;
-  if (full) {
 #pragma unroll
-    for (int h = 0; h < PPT; h += 4) {
-      const int4 cv = *(const int4*)(st.cell + s0 + h);
-      c[h] = cv.x; c[h + 1] = cv.y; c[h + 2] = cv.z; c[h + 3] = cv.w;
-      Vec4<R>::load(st.off + s0 + h, off + h);
-      Vec4<R>::load(st.vx + s0 + h, vx + h);
-      const ulonglong2 ia = *(const ulonglong2*)(st.id + s0 + h), ib = *(const ulonglong2*)(st.id + s0 + h + 2);
-      id[h] = ia.x; id[h + 1] = ia.y; id[h + 2] = ib.x; id[h + 3] = ib.y;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < PPT; q++) {
-      const bool in = s0 + q < Ns;
-      c[q] = in ? st.cell[s0 + q] : DEAD;
-      off[q] = in ? st.off[s0 + q] : (R)0;
-      vx[q] = in ? st.vx[s0 + q] : (R)0;
-      id[q] = in ? st.id[s0 + q] : 0;
-    }
+  for (int q = 0; q < PPT; q++) {
+    c[q] = P.c[q];
+    off[q] = P.off[q];
+    vx[q] = P.vx[q];
+    id[q] = P.id[q];
   }
+  const bool full = s0 + PPT - 1 < Ns;
   bool was_dead[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; q++) {
@@ -1030,10 +1168,10 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       if (cn == C.cmid) {
         R vy, vz;
         ld_yz(st, s0 + q, vy, vz);
-        diag_alive<R, S>(C, L.G, cn, vx[q], vy, vz);
+        diag_alive<R, S>(C, G, cn, vx[q], vy, vz);
       }
     } else if (S == 1) {
-      diag_alive<R, S>(C, L.G, cn, vx[q], (R)0, (R)0);
+      diag_alive<R, S>(C, G, cn, vx[q], (R)0, (R)0);
     }
   }
   if (run_cell >= 0) deposit_win(win, cnt_s, F_s, base, run_cell, run_val);
@@ -1101,19 +1239,125 @@ __device__ __forceinline__ double pmax_of(const Consts<R>& C, const Dev<R>& D, i
   return P;
 }
 
+// The workgroup's tiles of species S: tiles tb + u of the species' tile
+// sequence, u = u0, u0 + B.n, ... < nts (u0: this workgroup's first).  The deposit
+// window of a tile starts 64 cells below its first particle's cell as stored
+// before the push; every wave must use the same base, so the cell of the
+// segment's first tile is read before a barrier, and each next tile's during
+// the previous tile (before that tile's barrier).  (Loading each tile's
+// particles a tile ahead was measured no faster and costs 20 registers.)
+template <class R, int S, bool ELDS>
+__device__ __forceinline__ void push_loop(const Consts<R>& C, const Dev<R>& D, uint64_t (*win)[WIN], DiagLds& G,
+                                          const R* El, int64_t u0, int64_t nts, Blk B, int& buf, int64_t Ns,
+                                          uint32_t n, uint64_t T0, double pm, int& ps, int& abs0, int& abs1) {
+  const Store<R> st = D.st[S];
+  int base = u0 < nts ? win_base(st.cell[u0 * TILE]) : 0;
+  __syncthreads();
+  for (int64_t u = u0; u < nts; u += B.n, buf ^= 1) {
+    const bool more = u + B.n < nts;
+    const int32_t* nf = more ? st.cell + (u + B.n) * TILE : nullptr;
+    TileRegs<R> P;
+    load_tile(st, u * TILE, Ns, P);
+    const TileCount k = push_tile<R, S, ELDS>(C, D, win[buf], G, El, P, u * TILE, Ns, n, T0, pm, base, nf);
+    abs0 += k.abs0;
+    abs1 += k.abs1;
+    ps += k.pushed;
+    base = win_base(k.next_cell);
+  }
+}
+
+// The collisions of the candidates of this workgroup's tiles of species S
+// (the tiles u0, u0 + B.n, ... < nts of the species), in batches of up to FB
+// tiles.  The candidate records and counts were stored by every wave of the
+// workgroup (global memory), and the last window flush has to end before the
+// cross sections take its LDS.
+template <class R, int S, bool ELDS>
+__device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>& D, PushLds<R, ELDS>& L,
+                                                int64_t u0, int64_t nts, Blk B, uint32_t n) {
+  const int tid = threadIdx.x;
+  wg_global_sync();
+  if (u0 >= nts) return;
+  const int tab_n = C.tab_n[S];
+  if (tab_n > 0) {
+    // the species' compact table into LDS: 16-byte vectors, every load of a
+    // thread issued before its first store
+    constexpr int V4 = (TAB_LDS_BYTES / (int)sizeof(R) / 4 + TPB - 1) / TPB;
+    const int n4 = (tab_n + 3) / 4;
+    const R* src = D.sigc + C.tab_base[S];
+    R v[V4][4];
+#pragma unroll
+    for (int b = 0; b < V4; b++) {
+      const int i = tid + b * TPB;
+      if (i < n4) Vec4<R>::load(src + 4 * i, v[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < V4; b++) {
+      const int i = tid + b * TPB;
+      if (i < n4) Vec4<R>::store(L.u.tab + 4 * i, v[b]);
+    }
+  }
+  const TabRef<R> T = tab_n > 0 ? TabRef<R>{L.u.tab, true} : TabRef<R>{D.sig, false};
+  for (int64_t u = u0; u < nts;) {
+    int nbt = 0;
+    for (int64_t x = u; nbt < FB && x < nts; x += B.n) nbt++;
+    // prefix of the candidate counts of the batch's wave regions (one per thread)
+    {
+      static_assert(FB * 4 <= TPB, "one wave region per thread");
+      const int lane = tid & 63, wv = tid >> 6;
+      int x = 0;
+      if (tid < nbt * 4) {
+        const int64_t tile = u + (int64_t)(tid >> 2) * B.n;
+        x = D.tcnt[S][tile * 4 + (tid & 3)];
+      }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      if (lane == 63) L.wsum[wv] = x;
+      __syncthreads();
+      for (int w = 0; w < wv; w++) x += L.wsum[w];
+      L.cpre[tid + 1] = x;
+      if (tid == 0) L.cpre[0] = 0;
+    }
+    __syncthreads();
+    const int tot = L.cpre[nbt * 4];
+    // candidate e of the batch: record index in the species' list
+    auto rec = [&](int e) -> int64_t {
+      int lo = 0, hi = nbt * 4;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.cpre[mid] <= e) lo = mid;
+        else hi = mid;
+      }
+      const int64_t tile = u + (int64_t)(lo >> 2) * B.n;
+      return tile * TILE + (lo & 3) * WTILE + (e - L.cpre[lo]);
+    };
+    collide_range<R, S>(C, D, L.G, T, tot, rec, n);
+    __syncthreads();
+    u += (int64_t)nbt * B.n;
+  }
+}
+
 // ELDS: the node field (rounded to R, the values of E2) is staged in LDS
-// and the gather reads it there; for grids up to PushE<R>::MAXN cells
+// and the gather reads it there; for grids up to PushE<R>::MAXN cells.
+// The step's tiles (species by species, TILE particles each) are dealt to
+// the workgroups round robin.  A workgroup pushes all its tiles, then
+// collides their candidates species by species.  (Colliding each species
+// right after its tiles, with the species order reversed in every other
+// workgroup so that collisions overlap other workgroups' pushes, was
+// measured no faster: the push phase slowed by what the collisions gained.)
 template <class R, bool ELDS>
 __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
-  __shared__ PushLds<R> L;
-  __shared__ R El[ELDS ? PushE<R>::MAXN + 1 : 1];
+  __shared__ PushLds<R, ELDS> L;
+  R* El = L.u.p.El;
   const int tid = threadIdx.x;
   const int64_t nstep = D.ctr->step;
   const uint32_t n = (uint32_t)nstep;
   const bool ion = (nstep % C.nsub) == 0;
   if (B.x == 0 && tid == 0) D.ctr->step_push = nstep;
   diag_init(L.G);
-  for (int i = tid; i < 2 * WIN; i += TPB) L.win[i / WIN][i % WIN] = 0;
+  for (int i = tid; i < 2 * WIN; i += TPB) L.u.p.win[i / WIN][i % WIN] = 0;
   if (ELDS)
     for (int i = tid; i <= C.N; i += TPB) El[i] = (R)D.E[i];
   int64_t Ns[3], nt[3];
@@ -1127,101 +1371,49 @@ __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D,
     T0[s] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
     if (Ns[s] > 0 && pm[s] > 1.0 && B.x == 0 && tid == 0) atomicOr(&D.ctr->err, ERR_PMAX);
   }
-  const int64_t total = nt[0] + nt[1] + nt[2];
-  // first cell of tile t, as stored before this workgroup pushes it
-  auto first_cell = [&](int64_t t) -> const int32_t* {
-    if (t >= total) return nullptr;
-    if (t < nt[0]) return D.st[0].cell + t * TILE;
-    if (t < nt[0] + nt[1]) return D.st[1].cell + (t - nt[0]) * TILE;
-    return D.st[2].cell + (t - nt[0] - nt[1]) * TILE;
-  };
-  int base = 0;
-  if (const int32_t* f = first_cell(B.x)) base = win_base(*f);
-  __syncthreads();
-  int ps = 0, ae0 = 0, ae1 = 0, an0 = 0, an1 = 0, ap0 = 0, ap1 = 0;
-  int buf = 0;
-  for (int64_t t = B.x; t < total; t += B.n, buf ^= 1) {
-    const int32_t* nf = first_cell(t + B.n);
-    TileCount k;
-    if (t < nt[0]) {
-      k = push_tile<R, 0, ELDS>(C, D, L, El, buf, t * TILE, Ns[0], n, T0[0], pm[0], base, nf);
-      ae0 += k.abs0; ae1 += k.abs1;
-    } else if (t < nt[0] + nt[1]) {
-      k = push_tile<R, 1, ELDS>(C, D, L, El, buf, (t - nt[0]) * TILE, Ns[1], n, T0[1], pm[1], base, nf);
-      an0 += k.abs0; an1 += k.abs1;
-    } else {
-      k = push_tile<R, 2, ELDS>(C, D, L, El, buf, (t - nt[0] - nt[1]) * TILE, Ns[2], n, T0[2], pm[2], base, nf);
-      ap0 += k.abs0; ap1 += k.abs1;
-    }
-    ps += k.pushed;
-    base = win_base(k.next_cell);
-  }
-  // [electrode][species]
-  if (ae0) atomicAdd(&L.G.absorbed[0], ae0);
-  if (an0) atomicAdd(&L.G.absorbed[1], an0);
-  if (ap0) atomicAdd(&L.G.absorbed[2], ap0);
-  if (ae1) atomicAdd(&L.G.absorbed[3], ae1);
-  if (an1) atomicAdd(&L.G.absorbed[4], an1);
-  if (ap1) atomicAdd(&L.G.absorbed[5], ap1);
-  if (ps) atomicAdd(&L.G.psteps, ps);
-  // collisions of this workgroup's own candidates, in batches of up to FB
-  // tiles of one species
-  __syncthreads();
+  // this workgroup's first tile of each species: tiles are numbered through
+  // the species in order e, O-, O2+ and tile t goes to workgroup t mod B.n
+  int64_t u0[3];
   {
-    constexpr int FB = 16;
-    __shared__ int32_t cpre[FB * 4 + 1];
-    int64_t t = B.x;
-    while (t < total) {
-      const int s = t < nt[0] ? 0 : (t < nt[0] + nt[1] ? 1 : 2);
-      const int64_t tb = s == 0 ? 0 : (s == 1 ? nt[0] : nt[0] + nt[1]);
-      const int64_t tend = tb + nt[s];
-      int nbt = 0;
-      for (int64_t u = t; nbt < FB && u < tend; u += B.n) nbt++;
-      if (tid < 64) {
-        int x = 0;
-        if (tid < nbt * 4) {
-          const int64_t tile = t + (int64_t)(tid >> 2) * B.n - tb;
-          x = D.tcnt[s][tile * 4 + (tid & 3)];
-        }
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const int y = __shfl_up(x, d);
-          if (tid >= d) x += y;
-        }
-        if (tid < FB * 4) cpre[tid + 1] = x;
-        if (tid == 0) cpre[0] = 0;
-      }
-      __syncthreads();
-      const int tot = cpre[nbt * 4];
-      for (int e = tid; e < tot; e += TPB) {
-        int lo = 0, hi = nbt * 4;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (cpre[mid] <= e) lo = mid;
-          else hi = mid;
-        }
-        const int64_t tile = t + (int64_t)(lo >> 2) * B.n - tb;
-        const int64_t r = tile * TILE + (lo & 3) * WTILE + (e - cpre[lo]);
-        if (s == 0) collide_one<R, 0>(C, D, L.G, r, n);
-        else if (s == 1) collide_one<R, 1>(C, D, L.G, r, n);
-        else collide_one<R, 2>(C, D, L.G, r, n);
-      }
-      __syncthreads();
-      t += (int64_t)nbt * B.n;
+    int64_t tb = 0;
+    for (int s = 0; s < 3; s++) {
+      u0[s] = ((int64_t)B.x - tb % B.n + B.n) % B.n;
+      tb += nt[s];
     }
   }
+  int ps = 0, ab[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int buf = 0;
+  push_loop<R, 0, ELDS>(C, D, L.u.p.win, L.G, El, u0[0], nt[0], B, buf, Ns[0], n, T0[0], pm[0], ps, ab[0][0],
+                        ab[0][1]);
+  push_loop<R, 1, ELDS>(C, D, L.u.p.win, L.G, El, u0[1], nt[1], B, buf, Ns[1], n, T0[1], pm[1], ps, ab[1][0],
+                        ab[1][1]);
+  push_loop<R, 2, ELDS>(C, D, L.u.p.win, L.G, El, u0[2], nt[2], B, buf, Ns[2], n, T0[2], pm[2], ps, ab[2][0],
+                        ab[2][1]);
+  collide_species<R, 0, ELDS>(C, D, L, u0[0], nt[0], B, n);
+  collide_species<R, 1, ELDS>(C, D, L, u0[1], nt[1], B, n);
+  collide_species<R, 2, ELDS>(C, D, L, u0[2], nt[2], B, n);
+  // [electrode][species]
+  for (int s = 0; s < 3; s++) {
+    if (ab[s][0]) atomicAdd(&L.G.absorbed[s], ab[s][0]);
+    if (ab[s][1]) atomicAdd(&L.G.absorbed[3 + s], ab[s][1]);
+  }
+  if (ps) atomicAdd(&L.G.psteps, ps);
+  __syncthreads();
   diag_flush(C, D, L.G);
 }
 
+// the constants and device state are read from device memory (a copy per
+// buffer parity), not passed by value: a kilobyte of kernel arguments held in
+// scalar registers would spill into vector registers this kernel needs
 template <class R, bool ELDS>
-__global__ void __launch_bounds__(TPB) k_push(Consts<R> C, Dev<R> D) {
-  k_push_body<R, ELDS>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
+__global__ void __launch_bounds__(TPB, 3) k_push(const Consts<R>* __restrict__ Cp, const Dev<R>* __restrict__ Dp) {
+  k_push_body<R, ELDS>(*Cp, *Dp, Blk{(int)blockIdx.x, (int)gridDim.x});
 }
 
 // the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
 // [off[i], off[i + 1]))
 template <class R, bool ELDS>
-__global__ void __launch_bounds__(TPB) k_push_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
+__global__ void __launch_bounds__(TPB, 3) k_push_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
     const int32_t* __restrict__ off, int nd) {
   Blk b;
   const int i = batch_block(off, nd, b);
@@ -1311,7 +1503,7 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
         const R g = Sqrt(g2);
         const R Erel = C.hmu_c[pi] * g2;
         R sg = 0;
-        if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, q.chan, lookup(Erel)) * g;
+        if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, TS, q.chan, lookup(Erel)) * g;
         acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
       }
       L.rpart[r] = p;
@@ -1992,17 +2184,6 @@ __device__ inline void block_scan_excl(int32_t* a, int n, int32_t* wsum) {
 
 __device__ __forceinline__ int coul_bucket(uint32_t h, int nb) { return (int)(((uint64_t)h * (uint32_t)nb) >> 32); }
 
-// Global stores of this workgroup made visible to its other waves before
-// they read them.  The workgroup barrier alone waits only for LDS: each wave
-// first waits for its own vector memory operations (its stores reach the L2),
-// and after the barrier the CU's vector L1 is invalidated so that the reads
-// that follow come from the L2.  (A device-scope fence would also write the
-// L2 back, many times dearer, and is not needed within one workgroup.)
-__device__ __forceinline__ void wg_global_sync() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  asm volatile("buffer_inv sc0" ::: "memory");
-}
 
 // Pairing order of the Coulomb pass: the particles of one (species, cell)
 // segment ordered by (Philox(id, n, 16).x, id).  A counting sort into
