@@ -98,9 +98,11 @@ def main():
     if not args.no_autotune and args.warmup >= 1200:
         # part of the warm-up: six 200-step trials of the push grid (results do
         # not depend on it), the fastest kept
-        grid = d.autotune(200)
-        done = 1200
-        print(f"[bench] autotuned push grid: {grid} workgroups", file=sys.stderr, flush=True)
+        grid = d.autotune(100)
+        done = d.moments()["step"]
+        shape = d.launch_shape()
+        print(f"[bench] autotuned push kernel: {shape[0]} threads x {shape[1]} particles per thread, "
+              f"{grid} workgroups ({done} trial steps)", file=sys.stderr, flush=True)
     chunk = 500
     while done < args.warmup:
         k = min(chunk, args.warmup - done)
@@ -215,7 +217,8 @@ def main():
                                f"{sum(wl.n_init)} macro particles {tuple(wl.n_init)}",
                    "ion_subcycle": wl.ion_subcycle, "sort_every": wl.sort_every,
                    "coulomb_every": wl.coulomb_every, "coulomb_inter": bool(wl.coulomb_inter),
-                   "precision": args.precision, "push_grid": grid},
+                   "precision": args.precision, "push_grid": grid,
+                   "push_shape": list(d.launch_shape()[:2])},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -329,7 +332,17 @@ def sweep_main(args):
             done += c
             print(f"[bench] {label} {done}/{k}", file=sys.stderr, flush=True)
 
-    run(args.warmup, "warmup")
+    shape = None
+    if not args.no_autotune and args.warmup >= 600:
+        # part of the warm-up: batched steps on each tile shape and two push
+        # grids (real steps; results do not depend on them), the fastest kept
+        from paper_0705_0495_amd import autotune_batch
+        shape = autotune_batch(ds, 100)
+        print(f"[bench] autotuned batched push: {shape[0]} x {shape[1]}, {shape[2]} workgroups", file=sys.stderr,
+              flush=True)
+        run(args.warmup - 600, "warmup")
+    else:
+        run(args.warmup, "warmup")
     p0 = sum(d.moments()["particle_steps"] for d in ds)
     for d in ds:
         d.sync()
@@ -368,7 +381,8 @@ def sweep_main(args):
         "config": {"workload": f"sweep: {len(ds)} discharges, U~U[50,400] V, p~logU[5,100] Pa, L~U[2,6] cm, "
                                f"N_c in {{256,512,1024,2048}}, N~logU[1e5,4e6] ({ntot} particles in all), "
                                "dt=T/4000, sort and Coulomb every 10 steps",
-                   "graphs": not args.eager, "precision": args.precision},
+                   "graphs": not args.eager, "precision": args.precision,
+                   "push_shape": list(shape) if shape else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "whole step of all discharges (48 B per push over the wall clock)"},

@@ -191,20 +191,45 @@ int pic_kernel_time(pic_ctx* ctx, double* push_ms, int64_t* launches);
 
 /*
  * Launch shape of the fused particle kernel: number of persistent
- * workgroups (0 restores the occupancy-derived default).  Results do not
- * depend on it; the determinism tests vary it.
+ * workgroups (0 restores the occupancy-derived default of the current
+ * shape).  Results do not depend on it; the determinism tests vary it.
  */
 int pic_set_grid(pic_ctx* ctx, int32_t push_workgroups);
 
 /*
+ * Tile shape of the fused particle kernel: threads per workgroup and
+ * consecutive particles per thread (a tile is their product).  The shapes
+ * built are 256 x 4 (the default), 512 x 4 and 256 x 8; others return
+ * PIC_EINVAL (not sticky).  Setting a shape restores its default grid.
+ * Results do not depend on the shape.
+ */
+int pic_set_shape(pic_ctx* ctx, int32_t threads_per_workgroup, int32_t particles_per_thread);
+/* The shape and persistent grid the fused particle kernel launches with. */
+int pic_launch_shape(pic_ctx* ctx, int32_t* threads_per_workgroup, int32_t* particles_per_thread,
+                     int32_t* push_workgroups);
+
+/*
  * Autotuning of the launch shape: times the fused particle kernel (HIP
- * events) over steps_per_trial steps on each of a few persistent-grid sizes
- * (the occupancy default and 1, 2, 4, 6, 8 workgroups per CU) and keeps the
- * fastest; *chosen (may be NULL) receives its workgroup count.  The trial
- * steps are real steps of the discharge (6 x steps_per_trial of them, run
- * eagerly); results do not depend on the grid, so nothing else changes.
+ * events) over steps_per_trial steps on each tile shape and a few
+ * persistent-grid sizes (for the default shape the occupancy default and 1,
+ * 2, 4, 6, 8 workgroups per CU; for the others their occupancy default and
+ * three quarters of it) and keeps the fastest; *chosen (may be NULL)
+ * receives its workgroup count, pic_launch_shape the rest.  The trial steps
+ * are real steps of the discharge (run eagerly); results depend on neither
+ * the shape nor the grid, so nothing else changes.
  */
 int pic_autotune(pic_ctx* ctx, int64_t steps_per_trial, int32_t* chosen);
+
+/*
+ * Autotuning of the batched launches of pic_step_batch for the batch
+ * ctx[0..n): times steps_per_trial batched steps (real steps of every
+ * discharge) on each tile shape with two totals of push workgroups, and
+ * keeps the fastest for batches led by ctx[0].  The discharges must be
+ * batchable (as for pic_step_batch's batched path; else PIC_EINVAL, not
+ * sticky).  Outputs may be NULL.
+ */
+int pic_autotune_batch(pic_ctx* const* ctx, int n, int64_t steps_per_trial, int32_t* threads_per_workgroup,
+                       int32_t* particles_per_thread, int32_t* push_workgroups);
 
 /*
  * Graph replay (enable = 1) or eager launches (0, the default).  The launch

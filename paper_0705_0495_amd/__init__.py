@@ -5,6 +5,6 @@ discharges in Oxygen. Part 1: Modeling".
 The computation lives in libpic.so (HIP kernels for gfx950 behind the C ABI of
 include/pic.h); this package is its Python binding.
 """
-from .binding import Discharge, PicError, lib, step_batch, step_batch_static  # noqa: F401
+from .binding import Discharge, PicError, autotune_batch, lib, step_batch, step_batch_static  # noqa: F401
 
-__all__ = ["Discharge", "PicError", "lib", "step_batch", "step_batch_static"]
+__all__ = ["Discharge", "PicError", "autotune_batch", "lib", "step_batch", "step_batch_static"]

@@ -81,6 +81,10 @@ def lib():
     L.pic_autotune.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
     L.pic_step_batch.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
     L.pic_step_batch_static.argtypes = [P(C.c_void_p), C.c_int, C.c_int64]
+    L.pic_set_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.pic_launch_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+    L.pic_autotune_batch.argtypes = [P(C.c_void_p), C.c_int, C.c_int64, P(C.c_int32), P(C.c_int32),
+                                     P(C.c_int32)]
     L.pic_destroy.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]
     L.pic_last_error.restype = C.c_char_p
@@ -215,6 +219,16 @@ class Discharge:
         self._check(self.L.pic_autotune(self.h, steps_per_trial, C.byref(g)))
         return g.value
 
+    def set_shape(self, threads_per_workgroup, particles_per_thread):
+        """Tile shape of the fused particle kernel (256x4, 512x4 or 256x8)."""
+        self._check(self.L.pic_set_shape(self.h, threads_per_workgroup, particles_per_thread))
+
+    def launch_shape(self):
+        """(threads per workgroup, particles per thread, persistent workgroups) of the push."""
+        t, p, g = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        self._check(self.L.pic_launch_shape(self.h, C.byref(t), C.byref(p), C.byref(g)))
+        return t.value, p.value, g.value
+
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, 1 if enable else 0))
 
@@ -253,3 +267,18 @@ def step_batch_static(discharges, n_steps):
     if rc != 0:
         msg = L.pic_last_error(discharges[0].h)
         raise PicError(rc, msg.decode() if msg else "")
+
+
+def autotune_batch(discharges, steps_per_trial=50):
+    """Time the batched launches of pic_step_batch on every tile shape and two
+    push grids (real steps of every discharge) and keep the fastest for
+    batches led by discharges[0]; returns (threads, particles per thread,
+    workgroups)."""
+    L = discharges[0].L
+    arr = (C.c_void_p * len(discharges))(*[d.h for d in discharges])
+    t, p, g = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    rc = L.pic_autotune_batch(arr, len(discharges), steps_per_trial, C.byref(t), C.byref(p), C.byref(g))
+    if rc != 0:
+        msg = L.pic_last_error(discharges[0].h)
+        raise PicError(rc, msg.decode() if msg else "")
+    return t.value, p.value, g.value

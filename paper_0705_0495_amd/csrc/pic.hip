@@ -72,6 +72,10 @@ struct Base {
   virtual int64_t steps_done() const = 0;
   virtual int64_t chunk_period() const = 0;
   virtual int autotune(int64_t steps, int32_t* chosen) = 0;
+  virtual bool graphs_on() const = 0;
+  virtual int set_shape(int shape) = 0;
+  virtual void launch_shape(int32_t* shape, int32_t* grid) const = 0;
+  virtual int grid_default_of(int shape) const = 0;
 };
 
 }  // namespace
@@ -87,6 +91,9 @@ struct pic_ctx {
   hipEvent_t order_ev = nullptr;  // orders this context's stream before batched launches
   char* btab = nullptr;           // device tables of batches led by this context (grown, kept)
   size_t btab_bytes = 0;
+  int bshape = 0, bgrid = 0;         // push launch shape and grid of batches led by this context (0: default)
+  hipGraphExec_t bgraph = nullptr;  // one captured period of the batch led by this context
+  std::vector<char> bsig;           // what that capture depends on: tables, their address, steps
   std::string msg;
   int err = 0;
   bool timing = false;
@@ -130,6 +137,8 @@ struct Impl : Base {
   Dev<R> D;
   std::vector<void*> allocs;
   int grid_push = 0, grid_push_default = 0, grid_births = 64, grid_scatter = 0, ncu = 1;
+  int shape = 0;                    // launch shape of the push kernel (SHAPE_TPB/SHAPE_PPT index)
+  int grid_def[SHAPES] = {0, 0, 0};  // occupancy-derived persistent grid of each shape
   int64_t nstep = 0;  // steps enqueued
   bool elds = false;  // k_push stages the node field in LDS
   Dev<R> hD[2];             // host source of the device copies (kept until the copies are done)
@@ -162,17 +171,39 @@ struct Impl : Base {
   int64_t chunk() const override { return graphs ? period() : (int64_t)c->G.sort_every; }
   int64_t steps_done() const override { return nstep; }
   int64_t chunk_period() const override { return period(); }
+  bool graphs_on() const override { return graphs; }
 
-  // times the push kernel on a few persistent-grid sizes, steps_per_trial
-  // real steps each (results do not depend on the grid), and keeps the fastest
+  void launch_shape(int32_t* sh, int32_t* g) const override {
+    if (sh) *sh = shape;
+    if (g) *g = grid_push;
+  }
+  int grid_default_of(int sh) const override { return grid_def[sh]; }
+  int set_shape(int sh) override {
+    if (sh < 0 || sh >= SHAPES) return PIC_EINVAL;
+    shape = sh;
+    grid_push = grid_push_default = grid_def[sh];
+    drop_graph();
+    return 0;
+  }
+
+  // times the push kernel on a few launch shapes (threads per workgroup and
+  // particles per thread) and persistent-grid sizes, steps_per_trial real
+  // steps each (results depend on neither), and keeps the fastest
   int autotune(int64_t steps, int32_t* chosen) override {
     const bool was = c->timing;
-    std::vector<int> cand = {grid_push_default};
-    for (int k : {1, 2, 4, 6, 8}) cand.push_back(k * ncu);  // six trials in all
-    int best = grid_push_default;
+    std::vector<std::pair<int, int>> cand;
+    cand.push_back({0, grid_def[0]});
+    for (int k : {1, 2, 4, 6, 8})
+      if (k * ncu != grid_def[0]) cand.push_back({0, k * ncu});
+    for (int sh = 1; sh < SHAPES; sh++) {
+      cand.push_back({sh, grid_def[sh]});
+      cand.push_back({sh, std::max(1, (3 * grid_def[sh]) / 4)});
+    }
+    std::pair<int, int> best = cand[0];
     double tbest = 1e300;
-    for (int g : cand) {
-      set_grid(g);
+    for (const auto& sg : cand) {
+      set_shape(sg.first);
+      set_grid(sg.second);
       c->timing = true;
       c->timed_ms = 0;
       c->timed_launches = 0;
@@ -183,15 +214,16 @@ struct Impl : Base {
       const double t = c->timed_ms / (double)std::max<int64_t>(1, c->timed_launches);
       if (t < tbest) {
         tbest = t;
-        best = g;
+        best = sg;
       }
     }
     c->timing = was;
     c->timed_ms = 0;
     c->timed_launches = 0;
     c->ev_used = 0;
-    set_grid(best == grid_push_default ? 0 : best);
-    if (chosen) *chosen = best;
+    set_shape(best.first);
+    set_grid(best.second);
+    if (chosen) *chosen = best.second;
     return 0;
   }
 
@@ -403,8 +435,8 @@ struct Impl : Base {
     if ((rc = alloc(&D.bhist, (size_t)NBUCKET))) return rc;
     if ((rc = alloc(&D.perm, (size_t)D.nb_cap))) return rc;
     for (int s = 0; s < 3; s++) {
-      if ((rc = alloc(&D.cand[s], (size_t)D.cap[s] + TILE))) return rc;
-      if ((rc = alloc(&D.tcnt[s], (size_t)(D.cap[s] / WTILE + 8)))) return rc;
+      if ((rc = alloc(&D.cand[s], (size_t)D.cap[s] + TILE_MAX))) return rc;
+      if ((rc = alloc(&D.tcnt[s], (size_t)(D.cap[s] / WTILE_MIN + 8)))) return rc;
     }
     if ((rc = alloc(&D.ncand, 3))) return rc;
     D.req_cap = REQ_CAP;
@@ -471,9 +503,17 @@ struct Impl : Base {
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     elds = N <= PushE<R>::MAXN;
-    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &occ, elds ? (const void*)k_push<R, true> : (const void*)k_push<R, false>, TPB, 0));
-    grid_push = grid_push_default = std::max(1, ncu * std::max(1, occ));
+    {
+      const void* kf[SHAPES] = {
+          elds ? (const void*)k_push<R, true, Shape0> : (const void*)k_push<R, false, Shape0>,
+          elds ? (const void*)k_push<R, true, Shape1> : (const void*)k_push<R, false, Shape1>,
+          elds ? (const void*)k_push<R, true, Shape2> : (const void*)k_push<R, false, Shape2>};
+      for (int sh = 0; sh < SHAPES; sh++) {
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kf[sh], SHAPE_TPB[sh], 0));
+        grid_def[sh] = std::max(1, ncu * std::max(1, occ));
+      }
+    }
+    grid_push = grid_push_default = grid_def[shape];
     grid_scatter = std::max(1, ncu * 2);
 
 
@@ -578,6 +618,17 @@ struct Impl : Base {
     return 0;
   }
 
+  template <class SH>
+  void launch_push_sh(const Dev<R>* dpar) {
+    if (elds) hipLaunchKernelGGL((k_push<R, true, SH>), dim3(grid_push), dim3(SH::TPB), 0, c->stream, dC, dpar);
+    else hipLaunchKernelGGL((k_push<R, false, SH>), dim3(grid_push), dim3(SH::TPB), 0, c->stream, dC, dpar);
+  }
+  void launch_push(const Dev<R>* dpar) {
+    if (shape == 1) launch_push_sh<Shape1>(dpar);
+    else if (shape == 2) launch_push_sh<Shape2>(dpar);
+    else launch_push_sh<Shape0>(dpar);
+  }
+
   int step_eager(int64_t nsteps) {
     const int sort_every = c->G.sort_every;
     for (int64_t k = 0; k < nsteps; k++) {
@@ -595,8 +646,7 @@ struct Impl : Base {
         HIPCHK(c, hipEventRecord(e0, c->stream));
       }
       const Dev<R>* dpar = dD + (D.st[0].cell == dev_parity0_cell ? 0 : 1);
-      if (elds) hipLaunchKernelGGL((k_push<R, true>), dim3(grid_push), dim3(TPB), 0, c->stream, dC, dpar);
-      else hipLaunchKernelGGL((k_push<R, false>), dim3(grid_push), dim3(TPB), 0, c->stream, dC, dpar);
+      launch_push(dpar);
       if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
       HIPCHK(c, hipGetLastError());
       nstep++;
@@ -769,7 +819,7 @@ constexpr size_t batch_table_bytes(int n) {
 // device memory that no other work uses meanwhile).  Synchronising: returns
 // when the steps are done, so that the next call may rewrite the tables.
 template <class R>
-int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_cap) {
+int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_cap, bool allow_graph) {
   pic_ctx* c0 = ctx[0];
   hipStream_t st = c0->stream;
   if (batch_table_bytes<R>(n) > tab_cap) return fail(c0, PIC_EINVAL, "batch tables exceed their buffer");
@@ -799,7 +849,8 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_c
     const pic_geometry& G = ctx[i]->G;
     w[i] = (double)(G.n_init[0] + G.n_init[1] + G.n_init[2]) + 1.0;
   }
-  split_grid(w, im[0]->grid_push_default, &off[0]);
+  const int bshape = c0->bshape;
+  split_grid(w, c0->bgrid > 0 ? c0->bgrid : im[0]->grid_default_of(bshape), &off[0]);
   split_grid(w, im[0]->grid_scatter, &off[n + 1]);
   off[2 * (n + 1)] = 0;
   for (int i = 0; i < n; i++) off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + 3 * im[i]->C.N;
@@ -830,8 +881,8 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_c
   int64_t nstep = im[0]->nstep;
   int par = 0;
   int rc = 0;
-  for (int64_t k = 0; k < steps && !rc; k++) {
-    hipError_t e = launch_push_b<R>(dC, dD[par], n, g, elds, st);
+  auto one_step = [&]() -> hipError_t {
+    hipError_t e = launch_push_b<R>(dC, dD[par], n, g, elds, bshape, st);
     nstep++;
     const bool sort_now = nstep % sort_every == 0;
     if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, true, sort_now ? 0 : 1, st);
@@ -841,7 +892,68 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_c
       if (e == hipSuccess && ce > 0 && nstep % ce == 0) e = launch_coulomb_b<R>(dC, dD[par], n, g, inter_cells, st);
       if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, false, 1, st);
     }
+    return e;
+  };
+  // With graph replay on for the leading context, whole periods of the launch
+  // sequence (it repeats every P steps with the same arguments, and an even
+  // number of sorts returns the buffers) run as one captured graph.  The
+  // capture is kept with what it depends on (the tables' bytes and address)
+  // and reused by later calls for the same batch.
+  const int64_t P = im[0]->chunk_period();
+  const bool use_graph = allow_graph && im[0]->graphs_on();
+  std::vector<char> sig;
+  if (use_graph) {
+    auto put = [&](const void* p, size_t b) { sig.insert(sig.end(), (const char*)p, (const char*)p + b); };
+    put(&buf, sizeof(buf));
+    put(&n, sizeof(n));
+    put(&bshape, sizeof(bshape));
+    put(hc.data(), bc);
+    put(hd.data(), bd);
+    put(off.data(), bo);
+  }
+  for (int64_t k = 0; k < steps && !rc;) {
+    if (use_graph && nstep % P == 0 && steps - k >= P) {
+      // the capture also depends on which of the two device-state tables the
+      // period starts from
+      sig.push_back((char)par);
+      const bool same = c0->bgraph && c0->bsig == sig;
+      sig.pop_back();
+      if (!same) {
+        if (c0->bgraph) (void)hipGraphExecDestroy(c0->bgraph);
+        c0->bgraph = nullptr;
+        c0->bsig.clear();
+        hipGraph_t gr = nullptr;
+        const int64_t n0 = nstep;
+        const int par0 = par;
+        HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int64_t q = 0; q < P && e == hipSuccess; q++) e = one_step();
+        const hipError_t ee = hipStreamEndCapture(st, &gr);
+        nstep = n0;
+        if (e != hipSuccess || ee != hipSuccess || par != par0) {
+          if (gr) (void)hipGraphDestroy(gr);
+          rc = fail(c0, PIC_EDEVICE, std::string("batched capture: ") + hipGetErrorString(e != hipSuccess ? e : ee));
+          break;
+        }
+        const hipError_t ei = hipGraphInstantiate(&c0->bgraph, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess) {
+          c0->bgraph = nullptr;
+          rc = fail(c0, PIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+          break;
+        }
+        c0->bsig = sig;
+        c0->bsig.push_back((char)par);
+      }
+      const hipError_t e = hipGraphLaunch(c0->bgraph, st);
+      if (e != hipSuccess) rc = fail(c0, PIC_EDEVICE, std::string("batched graph: ") + hipGetErrorString(e));
+      nstep += P;
+      k += P;
+      continue;
+    }
+    const hipError_t e = one_step();
     if (e != hipSuccess) rc = fail(c0, PIC_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+    k++;
   }
   // every context stands where its own steps would have left it
   for (int i = 0; i < n; i++) {
@@ -1084,8 +1196,8 @@ int pic_step_batch(pic_ctx* const* ctx, int n, int64_t steps) {
     char* buf = nullptr;
     const int rc = batch_tables(ctx[0], bytes, &buf);
     if (rc) return rc;
-    return f64 ? batch_run<double>(ctx, n, steps, buf, ctx[0]->btab_bytes)
-               : batch_run<float>(ctx, n, steps, buf, ctx[0]->btab_bytes);
+    return f64 ? batch_run<double>(ctx, n, steps, buf, ctx[0]->btab_bytes, true)
+               : batch_run<float>(ctx, n, steps, buf, ctx[0]->btab_bytes, true);
   }
   // otherwise round robin in chunks of each context's period, so that every
   // stream holds queued work while the others run.  With Coulomb collisions
@@ -1142,14 +1254,82 @@ int pic_step_batch_static(pic_ctx* const* ctx, int n, int64_t steps) {
   if (steps == 0) return PIC_OK;
   char* buf = scratch_of(ctx[0]->dev);
   if (!buf) return fail(ctx[0], PIC_EDEVICE, "pic_step_batch_static: no device address of the static tables");
-  return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps, buf, SCRATCH_BYTES)
-                                         : batch_run<float>(ctx, n, steps, buf, SCRATCH_BYTES);
+  return ctx[0]->G.precision == PIC_FP64 ? batch_run<double>(ctx, n, steps, buf, SCRATCH_BYTES, false)
+                                         : batch_run<float>(ctx, n, steps, buf, SCRATCH_BYTES, false);
 }
 
 int pic_autotune(pic_ctx* c, int64_t steps_per_trial, int32_t* chosen) {
   if (!c || steps_per_trial <= 0) return PIC_EINVAL;
   if (c->err) return c->err;
   return c->impl->autotune(steps_per_trial, chosen);
+}
+
+int pic_set_shape(pic_ctx* c, int32_t tpb, int32_t ppt) {
+  if (!c) return PIC_EINVAL;
+  for (int sh = 0; sh < SHAPES; sh++)
+    if (SHAPE_TPB[sh] == tpb && SHAPE_PPT[sh] == ppt) return c->impl->set_shape(sh);
+  return reject(c, "pic_set_shape: " + std::to_string(tpb) + " x " + std::to_string(ppt) + " is not a shape built");
+}
+
+int pic_launch_shape(pic_ctx* c, int32_t* tpb, int32_t* ppt, int32_t* workgroups) {
+  if (!c) return PIC_EINVAL;
+  int32_t sh = 0, g = 0;
+  c->impl->launch_shape(&sh, &g);
+  if (tpb) *tpb = SHAPE_TPB[sh];
+  if (ppt) *ppt = SHAPE_PPT[sh];
+  if (workgroups) *workgroups = g;
+  return PIC_OK;
+}
+
+int pic_autotune_batch(pic_ctx* const* ctx, int n, int64_t steps_per_trial, int32_t* tpb, int32_t* ppt,
+                       int32_t* workgroups) {
+  if (!ctx || n < 1 || steps_per_trial <= 0) return PIC_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!ctx[i]) return PIC_EINVAL;
+    if (ctx[i]->err) return ctx[i]->err;
+  }
+  if (!batch_compatible(ctx, n)) return reject(ctx[0], "pic_autotune_batch: the discharges cannot be batched");
+  pic_ctx* c0 = ctx[0];
+  const bool f64 = c0->G.precision == PIC_FP64;
+  char* buf = nullptr;
+  int rc = batch_tables(c0, f64 ? batch_table_bytes<double>(n) : batch_table_bytes<float>(n), &buf);
+  if (rc) return rc;
+  std::vector<std::pair<int, int>> cand;
+  for (int sh = 0; sh < SHAPES; sh++) {
+    const int d = c0->impl->grid_default_of(sh);
+    cand.push_back({sh, d});
+    cand.push_back({sh, std::max(1, (3 * d) / 4)});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(c0, hipEventCreate(&e0));
+  HIPCHK(c0, hipEventCreate(&e1));
+  std::pair<int, int> best = cand[0];
+  float tbest = 3e38f;
+  for (const auto& sg : cand) {
+    c0->bshape = sg.first;
+    c0->bgrid = sg.second;
+    (void)hipEventRecord(e0, c0->stream);
+    rc = f64 ? batch_run<double>(ctx, n, steps_per_trial, buf, c0->btab_bytes, false)
+             : batch_run<float>(ctx, n, steps_per_trial, buf, c0->btab_bytes, false);
+    if (rc) break;
+    (void)hipEventRecord(e1, c0->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < tbest) {
+      tbest = ms;
+      best = sg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  c0->bshape = best.first;
+  c0->bgrid = best.second;
+  if (tpb) *tpb = SHAPE_TPB[best.first];
+  if (ppt) *ppt = SHAPE_PPT[best.first];
+  if (workgroups) *workgroups = best.second;
+  return PIC_OK;
 }
 
 int pic_set_grid(pic_ctx* c, int32_t g) {
@@ -1161,6 +1341,7 @@ int pic_set_grid(pic_ctx* c, int32_t g) {
 int pic_destroy(pic_ctx* c) {
   if (!c) return PIC_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
   if (c->btab) (void)hipFree(c->btab);
   if (c->order_ev) (void)hipEventDestroy(c->order_ev);
   delete c->impl;

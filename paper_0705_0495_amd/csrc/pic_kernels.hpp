@@ -18,10 +18,22 @@ constexpr int NCH = 19;
 constexpr int NPT = 897;
 constexpr int TS = 20;                 // table row stride: sig[k * TS + channel]
 constexpr int32_t DEAD = INT32_MIN;
-constexpr int TPB = 256;               // threads per push workgroup
-constexpr int PPT = 4;                 // consecutive particles per thread (16-byte vectors)
-constexpr int TILE = TPB * PPT;
-constexpr int WTILE = 64 * PPT;        // one wave's part of a tile
+// Launch shape of the fused particle kernel: TPB threads per workgroup, PPT
+// consecutive particles per thread (a multiple of 4: 16-byte vectors); a tile
+// is TPB * PPT consecutive particles, a wave's part of it WTILE.  The
+// autotuner chooses among the shapes built (SHAPES); results do not depend on
+// the shape.
+template <int TPB_, int PPT_>
+struct Shape {
+  static constexpr int TPB = TPB_, PPT = PPT_, TILE = TPB_ * PPT_, WTILE = 64 * PPT_, NW = TPB_ / 64;
+};
+using Shape0 = Shape<256, 4>;
+using Shape1 = Shape<512, 4>;
+using Shape2 = Shape<256, 8>;
+constexpr int SHAPES = 3;
+constexpr int SHAPE_TPB[SHAPES] = {256, 512, 256}, SHAPE_PPT[SHAPES] = {4, 4, 8};
+constexpr int TILE_MAX = 2048;         // the largest tile of the shapes built
+constexpr int WTILE_MIN = 256;         // the smallest wave part
 constexpr int WIN = 512;               // cells of the LDS deposit window
 constexpr int EEDF_MAX = 256;
 constexpr int FNEG_MAX = 2048;
@@ -172,6 +184,7 @@ struct Dev {
   Cand<R>* cand[3]; // candidates of the null-collision test: tile t of species s
                     // writes them to cand[s][t*TILE ...], wave w of the
                     // tile to cand[s][t*TILE + w*WTILE ...], count in tcnt[s][t*TILE/WTILE + w]
+                    // (TILE, WTILE of the launch shape)
   int32_t* tcnt[3]; // candidates per tile
   int32_t* ncand;   // [3] (unused)
   Request<R>* req;
@@ -931,7 +944,7 @@ __device__ __forceinline__ void collide_apply(const Consts<R>& C, const Dev<R>& 
 // record index), two per round and thread: both records, then both
 // candidates' other inputs are loaded before either is collided, so that each
 // dependent load is waited for once per pair.
-template <class R, int S, class Rec>
+template <class R, int S, int TPB, class Rec>
 __device__ __forceinline__ void collide_range(const Consts<R>& C, const Dev<R>& D, DiagLds& G, const TabRef<R>& T,
                                               int tot, Rec rec, uint32_t n) {
   const Store<R> st = D.st[S];
@@ -974,7 +987,7 @@ constexpr int FB = 64;  // tiles per collision batch (a species' tiles of one wo
 // windows of consecutive tiles (alternating) and, with ELDS, the node field;
 // the collision phase reuses the same bytes for the compact cross sections of
 // the gas channels of the species it collides
-template <class R, bool ELDS>
+template <class R, bool ELDS, class SH>
 struct PushLds {
   union __attribute__((aligned(16))) {
     struct {
@@ -984,8 +997,8 @@ struct PushLds {
     R tab[TAB_LDS_BYTES / sizeof(R)];
   } u;
   DiagLds G;
-  int32_t cpre[FB * 4 + 1];
-  int32_t wsum[TPB / 64];
+  int32_t cpre[FB * SH::NW + 1];
+  int32_t wsum[SH::NW];
 };
 
 template <class R> struct Vec4;
@@ -1022,15 +1035,15 @@ __device__ __forceinline__ void deposit_win(uint64_t* win, int32_t* cnt, int64_t
 }
 
 // one thread's PPT consecutive particles of a tile (16-byte vector loads)
-template <class R>
+template <class R, int PPT>
 struct TileRegs {
   int32_t c[PPT];
   R off[PPT], vx[PPT];
   uint64_t id[PPT];
 };
 
-template <class R>
-__device__ __forceinline__ void load_tile(const Store<R>& st, int64_t t0, int64_t Ns, TileRegs<R>& P) {
+template <class R, int PPT>
+__device__ __forceinline__ void load_tile(const Store<R>& st, int64_t t0, int64_t Ns, TileRegs<R, PPT>& P) {
   const int64_t s0 = t0 + (int64_t)PPT * threadIdx.x;
   if (s0 + PPT - 1 < Ns) {
 #pragma unroll
@@ -1072,11 +1085,12 @@ __device__ __forceinline__ int win_base(int32_t first_cell) { return (first_cell
 // starts while this one is flushed.  Each wave writes its candidates to its
 // own region of the list.  next_first points at the first cell of the
 // workgroup's next tile (null if none).
-template <class R, int S, bool ELDS>
+template <class R, int S, bool ELDS, class SH>
 __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>& D, uint64_t* win, DiagLds& G,
-                                               const R* El, const TileRegs<R>& P, int64_t t0, int64_t Ns,
+                                               const R* El, const TileRegs<R, SH::PPT>& P, int64_t t0, int64_t Ns,
                                                uint32_t n, uint64_t T0, double pmax, int base,
                                                const int32_t* next_first) {
+  constexpr int TPB = SH::TPB, PPT = SH::PPT, WTILE = SH::WTILE;
   TileCount tc = {0, 0, 0, DEAD};
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1246,19 +1260,20 @@ __device__ __forceinline__ double pmax_of(const Consts<R>& C, const Dev<R>& D, i
 // segment's first tile is read before a barrier, and each next tile's during
 // the previous tile (before that tile's barrier).  (Loading each tile's
 // particles a tile ahead was measured no faster and costs 20 registers.)
-template <class R, int S, bool ELDS>
+template <class R, int S, bool ELDS, class SH>
 __device__ __forceinline__ void push_loop(const Consts<R>& C, const Dev<R>& D, uint64_t (*win)[WIN], DiagLds& G,
                                           const R* El, int64_t u0, int64_t nts, Blk B, int& buf, int64_t Ns,
                                           uint32_t n, uint64_t T0, double pm, int& ps, int& abs0, int& abs1) {
+  constexpr int TILE = SH::TILE;
   const Store<R> st = D.st[S];
   int base = u0 < nts ? win_base(st.cell[u0 * TILE]) : 0;
   __syncthreads();
   for (int64_t u = u0; u < nts; u += B.n, buf ^= 1) {
     const bool more = u + B.n < nts;
     const int32_t* nf = more ? st.cell + (u + B.n) * TILE : nullptr;
-    TileRegs<R> P;
+    TileRegs<R, SH::PPT> P;
     load_tile(st, u * TILE, Ns, P);
-    const TileCount k = push_tile<R, S, ELDS>(C, D, win[buf], G, El, P, u * TILE, Ns, n, T0, pm, base, nf);
+    const TileCount k = push_tile<R, S, ELDS, SH>(C, D, win[buf], G, El, P, u * TILE, Ns, n, T0, pm, base, nf);
     abs0 += k.abs0;
     abs1 += k.abs1;
     ps += k.pushed;
@@ -1271,9 +1286,10 @@ __device__ __forceinline__ void push_loop(const Consts<R>& C, const Dev<R>& D, u
 // tiles.  The candidate records and counts were stored by every wave of the
 // workgroup (global memory), and the last window flush has to end before the
 // cross sections take its LDS.
-template <class R, int S, bool ELDS>
-__device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>& D, PushLds<R, ELDS>& L,
+template <class R, int S, bool ELDS, class SH>
+__device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>& D, PushLds<R, ELDS, SH>& L,
                                                 int64_t u0, int64_t nts, Blk B, uint32_t n) {
+  constexpr int TPB = SH::TPB, TILE = SH::TILE, WTILE = SH::WTILE, NW = SH::NW;
   const int tid = threadIdx.x;
   wg_global_sync();
   if (u0 >= nts) return;
@@ -1302,12 +1318,12 @@ __device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>
     for (int64_t x = u; nbt < FB && x < nts; x += B.n) nbt++;
     // prefix of the candidate counts of the batch's wave regions (one per thread)
     {
-      static_assert(FB * 4 <= TPB, "one wave region per thread");
+      static_assert(FB * NW <= TPB, "one wave region per thread");
       const int lane = tid & 63, wv = tid >> 6;
       int x = 0;
-      if (tid < nbt * 4) {
-        const int64_t tile = u + (int64_t)(tid >> 2) * B.n;
-        x = D.tcnt[S][tile * 4 + (tid & 3)];
+      if (tid < nbt * NW) {
+        const int64_t tile = u + (int64_t)(tid / NW) * B.n;
+        x = D.tcnt[S][tile * NW + (tid % NW)];
       }
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
@@ -1321,19 +1337,19 @@ __device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>
       if (tid == 0) L.cpre[0] = 0;
     }
     __syncthreads();
-    const int tot = L.cpre[nbt * 4];
+    const int tot = L.cpre[nbt * NW];
     // candidate e of the batch: record index in the species' list
     auto rec = [&](int e) -> int64_t {
-      int lo = 0, hi = nbt * 4;
+      int lo = 0, hi = nbt * NW;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (L.cpre[mid] <= e) lo = mid;
         else hi = mid;
       }
-      const int64_t tile = u + (int64_t)(lo >> 2) * B.n;
-      return tile * TILE + (lo & 3) * WTILE + (e - L.cpre[lo]);
+      const int64_t tile = u + (int64_t)(lo / NW) * B.n;
+      return tile * TILE + (lo % NW) * WTILE + (e - L.cpre[lo]);
     };
-    collide_range<R, S>(C, D, L.G, T, tot, rec, n);
+    collide_range<R, S, TPB>(C, D, L.G, T, tot, rec, n);
     __syncthreads();
     u += (int64_t)nbt * B.n;
   }
@@ -1347,9 +1363,10 @@ __device__ __forceinline__ void collide_species(const Consts<R>& C, const Dev<R>
 // right after its tiles, with the species order reversed in every other
 // workgroup so that collisions overlap other workgroups' pushes, was
 // measured no faster: the push phase slowed by what the collisions gained.)
-template <class R, bool ELDS>
+template <class R, bool ELDS, class SH>
 __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D, Blk B) {
-  __shared__ PushLds<R, ELDS> L;
+  constexpr int TPB = SH::TPB, TILE = SH::TILE;
+  __shared__ PushLds<R, ELDS, SH> L;
   R* El = L.u.p.El;
   const int tid = threadIdx.x;
   const int64_t nstep = D.ctr->step;
@@ -1383,15 +1400,15 @@ __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D,
   }
   int ps = 0, ab[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   int buf = 0;
-  push_loop<R, 0, ELDS>(C, D, L.u.p.win, L.G, El, u0[0], nt[0], B, buf, Ns[0], n, T0[0], pm[0], ps, ab[0][0],
+  push_loop<R, 0, ELDS, SH>(C, D, L.u.p.win, L.G, El, u0[0], nt[0], B, buf, Ns[0], n, T0[0], pm[0], ps, ab[0][0],
                         ab[0][1]);
-  push_loop<R, 1, ELDS>(C, D, L.u.p.win, L.G, El, u0[1], nt[1], B, buf, Ns[1], n, T0[1], pm[1], ps, ab[1][0],
+  push_loop<R, 1, ELDS, SH>(C, D, L.u.p.win, L.G, El, u0[1], nt[1], B, buf, Ns[1], n, T0[1], pm[1], ps, ab[1][0],
                         ab[1][1]);
-  push_loop<R, 2, ELDS>(C, D, L.u.p.win, L.G, El, u0[2], nt[2], B, buf, Ns[2], n, T0[2], pm[2], ps, ab[2][0],
+  push_loop<R, 2, ELDS, SH>(C, D, L.u.p.win, L.G, El, u0[2], nt[2], B, buf, Ns[2], n, T0[2], pm[2], ps, ab[2][0],
                         ab[2][1]);
-  collide_species<R, 0, ELDS>(C, D, L, u0[0], nt[0], B, n);
-  collide_species<R, 1, ELDS>(C, D, L, u0[1], nt[1], B, n);
-  collide_species<R, 2, ELDS>(C, D, L, u0[2], nt[2], B, n);
+  collide_species<R, 0, ELDS, SH>(C, D, L, u0[0], nt[0], B, n);
+  collide_species<R, 1, ELDS, SH>(C, D, L, u0[1], nt[1], B, n);
+  collide_species<R, 2, ELDS, SH>(C, D, L, u0[2], nt[2], B, n);
   // [electrode][species]
   for (int s = 0; s < 3; s++) {
     if (ab[s][0]) atomicAdd(&L.G.absorbed[s], ab[s][0]);
@@ -1405,19 +1422,21 @@ __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D,
 // the constants and device state are read from device memory (a copy per
 // buffer parity), not passed by value: a kilobyte of kernel arguments held in
 // scalar registers would spill into vector registers this kernel needs
-template <class R, bool ELDS>
-__global__ void __launch_bounds__(TPB, 3) k_push(const Consts<R>* __restrict__ Cp, const Dev<R>* __restrict__ Dp) {
-  k_push_body<R, ELDS>(*Cp, *Dp, Blk{(int)blockIdx.x, (int)gridDim.x});
+template <class R, bool ELDS, class SH>
+__global__ void __launch_bounds__(SH::TPB, 3) k_push(const Consts<R>* __restrict__ Cp,
+                                                                   const Dev<R>* __restrict__ Dp) {
+  k_push_body<R, ELDS, SH>(*Cp, *Dp, Blk{(int)blockIdx.x, (int)gridDim.x});
 }
 
 // the same for a batch of discharges over a 1-D grid (workgroups of discharge i:
 // [off[i], off[i + 1]))
-template <class R, bool ELDS>
-__global__ void __launch_bounds__(TPB, 3) k_push_b(const Consts<R>* __restrict__ Cs, const Dev<R>* __restrict__ Ds,
-    const int32_t* __restrict__ off, int nd) {
+template <class R, bool ELDS, class SH>
+__global__ void __launch_bounds__(SH::TPB, 3) k_push_b(const Consts<R>* __restrict__ Cs,
+                                                                     const Dev<R>* __restrict__ Ds,
+                                                                     const int32_t* __restrict__ off, int nd) {
   Blk b;
   const int i = batch_block(off, nd, b);
-  k_push_body<R, ELDS>(Cs[i], Ds[i], b);
+  k_push_body<R, ELDS, SH>(Cs[i], Ds[i], b);
 }
 
 // ---------------------------------------------------------------------------
@@ -2972,11 +2991,19 @@ inline hipError_t launch_tail_b(const Consts<R>* C, const Dev<R>* D, int nd, int
   return hipGetLastError();
 }
 
+template <class R, class SH>
+inline void launch_push_b_sh(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g, bool elds,
+                             hipStream_t st) {
+  if (elds) hipLaunchKernelGGL((k_push_b<R, true, SH>), dim3(g.n_push), dim3(SH::TPB), 0, st, C, D, g.push, nd);
+  else hipLaunchKernelGGL((k_push_b<R, false, SH>), dim3(g.n_push), dim3(SH::TPB), 0, st, C, D, g.push, nd);
+}
+// shape: index into the shapes built (SHAPE_TPB, SHAPE_PPT)
 template <class R>
 inline hipError_t launch_push_b(const Consts<R>* C, const Dev<R>* D, int nd, const BatchGrids& g, bool elds,
-                                hipStream_t st) {
-  if (elds) hipLaunchKernelGGL((k_push_b<R, true>), dim3(g.n_push), dim3(TPB), 0, st, C, D, g.push, nd);
-  else hipLaunchKernelGGL((k_push_b<R, false>), dim3(g.n_push), dim3(TPB), 0, st, C, D, g.push, nd);
+                                int shape, hipStream_t st) {
+  if (shape == 1) launch_push_b_sh<R, Shape1>(C, D, nd, g, elds, st);
+  else if (shape == 2) launch_push_b_sh<R, Shape2>(C, D, nd, g, elds, st);
+  else launch_push_b_sh<R, Shape0>(C, D, nd, g, elds, st);
   return hipGetLastError();
 }
 

@@ -130,14 +130,20 @@ def test_one_rf_cycle_diagnostics_match_oracle():
     assert np.array_equal(m["phi"], phi / wl.steps_per_period)
 
 
-def test_results_independent_of_launch_shape():
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_results_independent_of_launch_shape(prec):
+    """Tile shapes (threads per workgroup x particles per thread) and
+    persistent grids of the push kernel change no result."""
     wl = ragged_small()
     sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     ref = None
-    for grid in (0, 1, 7, 61):
-        g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    for shape, grid in (((256, 4), 0), ((256, 4), 1), ((256, 4), 7), ((256, 4), 61), ((512, 4), 0), ((512, 4), 3),
+                        ((256, 8), 0), ((256, 8), 5)):
+        g = _gpu()(wl, sig, thr, loss, precision=prec)
+        g.set_shape(*shape)
         if grid:
             g.set_grid(grid)
+        assert g.launch_shape()[:2] == shape
         g.step(60)
         out = [_by_id(g.particles(s)) for s in range(3)]
         ev = g.moments()["events"]
@@ -590,6 +596,32 @@ def test_served_discharges_match_alone():
         alone.close()
 
 
+def test_batch_autotune_and_shapes_change_no_result():
+    """The batch autotuner's trials are ordinary batched steps; a batch on each
+    tile shape, with graph replay of whole periods, ends as each discharge
+    stepped alone."""
+    from paper_0705_0495_amd import autotune_batch, step_batch
+    from pic_inputs import sweep
+    wls = [w.scaled(0.02, name=w.name) for w in sweep(64)[:3]]
+    sig, thr, loss = build_tables()
+    batch = [_gpu()(w, sig, thr, loss, precision="fp32") for w in wls]
+    t, p, g = autotune_batch(batch, 20)
+    assert (t, p) in ((256, 4), (512, 4), (256, 8)) and g > 0
+    done = 6 * 20
+    for d in batch:
+        d.set_graphs(True)
+    step_batch(batch, 40)
+    done += 40
+    for w, d in zip(wls, batch):
+        alone = _gpu()(w, sig, thr, loss, precision="fp32")
+        alone.set_shape(256, 8)
+        alone.step(done)
+        alone.sync()
+        _same_state(_state(alone), _state(d), w.name)
+        alone.close()
+        d.close()
+
+
 def test_autotune_changes_no_result():
     """The grid autotuner's trial steps are ordinary steps: afterwards the
     discharge equals a twin stepped the same number of times on the default
@@ -600,7 +632,7 @@ def test_autotune_changes_no_result():
     b = _gpu()(wl, sig, thr, loss, precision="fp32")
     g = a.autotune(10)
     assert g > 0
-    b.step(60)
+    b.step(a.moments()["step"])
     _same_state(_state(a), _state(b), "after tuning")
     a.step(25)
     b.step(25)
