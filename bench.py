@@ -6,8 +6,10 @@ Workload (default): the large single discharge -- 6 cm gap, 4096 cells, O2 at
 fixed-point charge, FP64 field solve.  A step is one pass of the whole hot
 path: field solve, fused gather/push/absorb/null-collision MCC/deposit of every
 species, partner reactions, births, and every 10th step the cell sort followed
-by the intra-species Coulomb collisions.  Default: 1 rf cycle (8000 steps) of
-warm-up, then 5 rf cycles (40000 steps) timed.
+by the intra-species Coulomb collisions.  Before the W warm-up steps the
+discharge gets a warm start of --warm-start-cycles rf cycles (default 1:
+8000 steps, whose first ~1000 are the autotuner's trials of launch shapes and
+grids); default W = 2000 and K = 40000 (5 rf cycles timed).
 
 Prints one JSON line.  ``value`` is particle pushes per second over the timed
 steps (inputs resident in HBM, wall clock between two stream synchronisations).
@@ -20,7 +22,11 @@ HIP events recorded on the library's stream around every launch.  The kernel
 itself never touches vy and vz of the ~95 % of particles that do not collide
 (the field is along x); ``achieved_touched``/``frac_touched`` count only the
 32 B (FP32; 48 B in FP64) it must move for every particle.  ``traffic`` is the
-kernel's measured HBM bytes per launch (rocprofv3 counters, profiles/).
+kernel's HBM bytes per launch from rocprofv3 counters (profiles/, taken in a
+separate run of the same kernel sources; null when the sources changed since),
+and ``frac_traffic`` the fraction of peak those bytes reach.  ``host`` names the
+CPU model and core counts; the CPU baseline's all-cores leg uses every core
+available to the process.
 
 Other modes: ``--workload sweep`` (many discharges advanced together),
 ``--workload serve`` (the serving loop over a request stream),
@@ -45,19 +51,43 @@ BYTES_PER_STEP = {"fp32": 48, "fp64": 80}      # whole particle state read and w
 BYTES_TOUCHED = {"fp32": 32, "fp64": 48}       # cell, off, vx read and written, id read
 TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "traffic_k_push.json"),
                  "fp64": os.path.join(ROOT, "profiles", "traffic_k_push_fp64.json")}
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0705_0495_amd", "csrc", f) for f in ("pic_kernels.hpp", "pic.hip")]
+
+
+def kernel_source_sha():
+    """Hash of the HIP sources: counter files name the sources they were taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def host_info():
+    """CPU model and core counts of the host the benchmark runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cores_available": len(os.sched_getaffinity(0))}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40000)
-    ap.add_argument("--warmup", type=int, default=8000)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="large", choices=["small", "prod", "large", "sweep", "serve", "ablation"])
     ap.add_argument("--cycles", type=int, default=20, help="ablation: rf cycles per run")
-    ap.add_argument("--requests", type=int, default=64, help="serve: requests from the sweep distribution")
+    ap.add_argument("--requests", type=int, default=32, help="serve: requests in the stream")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrivals per second (0: all at once)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory for particle stores")
-    ap.add_argument("--max-cycles", type=int, default=2, help="serve: rf cycles per request at most")
+    ap.add_argument("--max-cycles", type=int, default=400, help="serve: rf cycles per request at most")
+    ap.add_argument("--stream", default="served", choices=["served", "sweep"], help="serve: request distribution")
     ap.add_argument("--discharges", type=int, default=64, help="sweep: number of discharges")
     ap.add_argument("--eager", action="store_true", help="sweep: no graph replay")
     ap.add_argument("--sequential", action="store_true", help="sweep: also time the discharges one after another")
@@ -68,7 +98,10 @@ def main():
                     help="large/prod/small: unlike-species Coulomb collisions as well (off in the paper's runs)")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--cpu-scale", type=float, default=1.0 / 32)
-    ap.add_argument("--cpu-cores", type=int, default=16, help="all-cores baseline: oracle instances at most")
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="all-cores baseline: oracle instances (0: every core available to the process)")
+    ap.add_argument("--warm-start-cycles", type=float, default=1.0,
+                    help="large/prod/small: rf cycles run before the warm-up (the discharge's warm start)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the discharge is not sharded "
@@ -93,26 +126,30 @@ def main():
     d = Discharge(wl, sig, thr, loss, precision=args.precision, capacity=cap)
     print(f"[bench] created {args.workload} ({sum(wl.n_init)} particles) in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
-    done = 0
+    # warm start (the configuration times whole rf cycles of a running
+    # discharge, not the initial load): warm_start_cycles rf cycles, whose
+    # first steps are the autotuner's trials of launch shapes and grids
+    # (real steps; results depend on neither)
+    warm = int(round(args.warm_start_cycles * wl.steps_per_period))
     grid = None
-    if not args.no_autotune and args.warmup >= 1200:
-        # part of the warm-up: six 200-step trials of the push grid (results do
-        # not depend on it), the fastest kept
+    done = 0
+    if not args.no_autotune and warm >= 1000:
         grid = d.autotune(100)
         done = d.moments()["step"]
         shape = d.launch_shape()
         print(f"[bench] autotuned push kernel: {shape[0]} threads x {shape[1]} particles per thread, "
               f"{grid} workgroups ({done} trial steps)", file=sys.stderr, flush=True)
     chunk = 500
-    while done < args.warmup:
-        k = min(chunk, args.warmup - done)
+    target = warm + args.warmup
+    while done < target:
+        k = min(chunk, target - done)
         tw = time.perf_counter()
         d.step(k)
         d.sync()
         done += k
         m = d.moments()
-        print(f"[bench] warmup {done}/{args.warmup}: {(time.perf_counter() - tw) * 1e3 / k:.3f} ms/step, "
-              f"alive {m['alive']}", file=sys.stderr, flush=True)
+        print(f"[bench] {'warm start' if done <= warm else 'warmup'} {done}/{target}: "
+              f"{(time.perf_counter() - tw) * 1e3 / k:.3f} ms/step, alive {m['alive']}", file=sys.stderr, flush=True)
     m0 = d.moments()
     d.timing(True)
     d.sync()
@@ -140,21 +177,33 @@ def main():
     avg_launch_s = (push_ms / 1e3) / max(launches, 1)
     bytes_per_launch = bpp * psteps / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    # measured HBM bytes per launch: FETCH_SIZE + WRITE_SIZE counters of the same
-    # kernel (calibrated against a copy of known size), scaled to this run's pushes
+    # HBM bytes per launch measured by counters (FETCH_SIZE + WRITE_SIZE of
+    # the same kernel in two rocprofv3 --pmc runs, calibrated against a copy
+    # of known size; profiles/), per push, scaled to this run's pushes per
+    # launch.  Not measured in this run: taken from the file, and only if the
+    # file names the kernel sources this library was built from.
     traffic = None
+    traffic_note = None
     tfile = TRAFFIC_FILES.get(args.precision)
     if tfile and os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if t.get("workload") == args.workload and t.get("precision") == args.precision:
+            if t.get("workload") != args.workload or t.get("precision") != args.precision:
+                traffic_note = "no counter file for this workload"
+            elif t.get("source_sha") != kernel_source_sha():
+                traffic_note = "counters in profiles/ predate the current kernel sources"
+            else:
                 traffic = round(t["bytes_per_push"] * psteps / max(launches, 1))
+                traffic_note = f"from {os.path.relpath(tfile, ROOT)} ({t['bytes_per_push']} B per push)"
         except (OSError, ValueError, KeyError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_push", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-                "bytes_per_push": bpp}
+                "bytes_per_push": bpp, "traffic_source": traffic_note}
+    if traffic:
+        roofline["achieved_traffic"] = round(traffic / avg_launch_s / 1e9, 1)
+        roofline["frac_traffic"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     touched = BYTES_TOUCHED[args.precision] * psteps / max(launches, 1) / avg_launch_s / 1e9
     roofline["achieved_touched"] = round(touched, 1)
     roofline["frac_touched"] = round(touched / HBM_PEAK_GBS, 4)
@@ -179,7 +228,8 @@ def main():
         # stepped in threads (the oracle is C behind ctypes, which releases
         # the GIL); created one after another, stepped together
         import threading
-        ncores = max(1, min(len(os.sched_getaffinity(0)), args.cpu_cores))
+        avail = len(os.sched_getaffinity(0))
+        ncores = max(1, min(avail, args.cpu_cores) if args.cpu_cores > 0 else avail)
         steps_mc = max(1, args.cpu_steps // 2)
         inst = [O.Oracle(swl, sig, thr, loss, precision=args.precision) for _ in range(ncores)]
         p0 = [i.counters()[2]["psteps"] for i in inst]
@@ -221,6 +271,7 @@ def main():
                    "push_shape": list(d.launch_shape()[:2])},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "host": host_info(),
     }
     print(json.dumps(out), flush=True)
     if wl.coulomb_inter:
@@ -395,16 +446,21 @@ def sweep_main(args):
 
 
 def serve_main(args):
-    """The serving loop on a finite stream of requests drawn from the sweep
-    distribution (Poisson arrivals at --rate per second), each run for at
-    most --max-cycles rf cycles or to its steady-state detector, under a
-    device-memory budget.  ``value`` is the aggregate particle pushes per
-    second over the whole stream; the JSON line also gives the requests'
-    time from arrival to retirement (p50, p99)."""
+    """The serving loop on a finite stream of requests (Poisson arrivals at
+    --rate per second), each run to its steady-state detector (the rf-cycle
+    averaged ion count changes by less than 1 % against 50 cycles earlier,
+    twice in a row) or --max-cycles rf cycles, under a device-memory budget,
+    admitted at launch-period boundaries.  Requests: --stream served (default;
+    small discharges that reach steady state in about a hundred rf cycles) or
+    sweep (the batched sweep's distribution, which does not reach it within
+    any cap that fits here).  ``value`` is the aggregate particle pushes per
+    second over the whole stream; the line also gives p50/p99 time from
+    arrival to steady state (over the requests that reached it) and to
+    retirement."""
     import numpy as np
     from paper_0705_0495_amd.serve import Request, Server
-    from pic_inputs import build_tables, sweep
-    wls = sweep(args.requests, seed=705049600)
+    from pic_inputs import build_tables, served_stream, sweep
+    wls = served_stream(args.requests) if args.stream == "served" else sweep(args.requests, seed=705049600)
     rng = np.random.default_rng(705049601)
     gaps = rng.exponential(1.0 / args.rate, size=len(wls)) if args.rate > 0 else np.zeros(len(wls))
     tables = build_tables()
@@ -418,9 +474,9 @@ def serve_main(args):
         if not s.active and s.queue and s.queue[0].arrival > time.perf_counter():
             time.sleep(min(1.0, s.queue[0].arrival - time.perf_counter()))
             continue
-        done = s.step_cycle()
+        done = s.step_quantum()
         for r in done:
-            print(f"[bench] request {r.rid} done after {r.cycles} cycles, "
+            print(f"[bench] request {r.rid} {'steady' if r.steady else 'capped'} after {r.cycles} cycles, "
                   f"{r.t_done - r.t_arrival:.2f}s from arrival", file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t0
     lat = s.latency()
@@ -438,11 +494,12 @@ def serve_main(args):
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"serve: {len(wls)} requests from the sweep distribution, Poisson arrivals at "
-                               f"{args.rate:g}/s, at most {args.max_cycles} rf cycles each, "
-                               f"{args.budget_gb:g} GiB budget",
+        "config": {"workload": f"serve: {len(wls)} requests ({args.stream} stream), Poisson arrivals at "
+                               f"{args.rate:g}/s, run to steady state or {args.max_cycles} rf cycles, "
+                               f"{args.budget_gb:g} GiB budget, admission at launch-period boundaries",
                    "precision": args.precision},
         "latency_s": {"p50": round(lat["p50_s"], 3), "p99": round(lat["p99_s"], 3)},
+        "time_to_steady_state_s": {"p50": round(lat["ss_p50_s"], 3), "p99": round(lat["ss_p99_s"], 3)},
         "served": lat["served"], "steady": lat["steady"], "wall_s": round(elapsed, 2),
         "roofline": None,
         "cpu_baseline": None,

@@ -2,10 +2,14 @@
 
 Requests -- the parameters of one discharge each -- wait in a queue.  They are
 admitted while the device memory their particle stores need stays within a
-budget, advanced together one rf cycle at a time (``step_batch``: one launch
+budget, advanced together one quantum at a time (``step_batch``: one launch
 per kernel for every active discharge, all standing at the same phase of the
 step sequence), and retired when their steady-state detector fires or they
-reach their cycle limit; the memory they free admits the next requests.
+reach their cycle limit; the memory they free admits the next requests.  The
+quantum is the launch period of the step sequence (twice the least common
+multiple of the sort and Coulomb intervals; it divides an rf cycle), so an
+arrival waits at most one period for admission, and a discharge admitted at
+a period boundary stands at the same phase as the running ones.
 
 Steady state, as Sec. II defines the end of a run: the moments no longer
 change when averaged over an rf cycle.  The detector watches the
@@ -20,6 +24,7 @@ to single ones).
 from __future__ import annotations
 
 import dataclasses
+import math
 import time
 from collections import deque
 
@@ -45,10 +50,10 @@ class Request:
 class Result:
     rid: int
     cycles: int
-    steady: bool
+    steady: bool                # retired by the steady-state detector (else by the cycle limit)
     t_arrival: float
     t_admit: float
-    t_done: float
+    t_done: float               # when the detector fired or the limit was reached
     ions: list                  # cycle-averaged ion count per completed cycle
     pushes: int = 0             # particle pushes of the discharge
 
@@ -71,6 +76,14 @@ class SteadyState:
         change = abs(self.values[-1] - ref) / max(abs(ref), 1e-300)
         self.hits = self.hits + 1 if change < self.tol else 0
         return self.hits >= 2
+
+
+def launch_period(wl) -> int:
+    """Steps after which the library's launch sequence repeats: twice the
+    least common multiple of the sort and Coulomb intervals."""
+    a = int(wl.sort_every)
+    b = int(wl.coulomb_every) if wl.coulomb_every > 0 else 1
+    return 2 * (a // math.gcd(a, b)) * b
 
 
 def capacity(wl) -> list:
@@ -119,17 +132,21 @@ class Server:
         self.step_batch = step_batch
         self.clock = clock
         self.queue: deque = deque()
-        self.active: list = []          # [request, discharge, detector, t_admit, bytes]
+        self.active: list = []          # [request, discharge, detector, t_admit, bytes, steps]
         self.results: list[Result] = []
         self.used = 0
         self.cycle_steps = None
+        self.quantum = None
         self.period = None
 
     def submit(self, req: Request) -> None:
         wl = req.workload
         key = (wl.steps_per_period, wl.sort_every, wl.coulomb_every)
         if self.cycle_steps is None:
-            self.cycle_steps, self.period = wl.steps_per_period, key
+            q = launch_period(wl)
+            if wl.steps_per_period % q != 0:
+                raise ValueError("the launch period must divide an rf cycle")
+            self.cycle_steps, self.quantum, self.period = wl.steps_per_period, q, key
         elif key != self.period:
             raise ValueError("requests of one server share steps per rf cycle, sort and Coulomb periods")
         if bytes_needed(wl, self.precision) > self.budget:
@@ -151,18 +168,23 @@ class Server:
             self.queue.popleft()
             d = self.backend(req.workload, *self.tables, precision=self.precision, capacity=capacity(req.workload))
             self.used += need
-            self.active.append([req, d, SteadyState(req.window, req.tol), self.clock(), need])
+            self.active.append([req, d, SteadyState(req.window, req.tol), self.clock(), need, 0])
 
-    def step_cycle(self) -> list:
-        """Admit what fits, advance every active discharge by one rf cycle,
+    def step_quantum(self) -> list:
+        """Admit what fits, advance every active discharge by one launch
+        period, feed the detectors of those that completed an rf cycle,
         retire the finished ones; returns the results retired now."""
         self._admit()
         if not self.active:
             return []
-        self.step_batch([a[1] for a in self.active], self.cycle_steps)
+        self.step_batch([a[1] for a in self.active], self.quantum)
         done, keep = [], []
         for a in self.active:
-            req, d, det, t_admit, need = a
+            a[5] += self.quantum
+            req, d, det, t_admit, need, steps = a
+            if steps % self.cycle_steps != 0:
+                keep.append(a)
+                continue
             m = d.moments()
             steady = det.feed(cycle_ions(m, req.workload))
             if steady or m["cycles"] >= req.max_cycles:
@@ -176,19 +198,29 @@ class Server:
         self.results.extend(done)
         return done
 
+    def step_cycle(self) -> list:
+        """Advance by whole launch periods until one rf cycle has passed."""
+        done = []
+        for _ in range(self.cycle_steps // self.quantum if self.quantum else 1):
+            done += self.step_quantum()
+        return done
+
     def run(self) -> list:
         """Serve until the queue and the active set are empty."""
         while self.queue or self.active:
             if not self.active and self.queue and self.queue[0].arrival > self.clock():
                 time.sleep(min(1.0, self.queue[0].arrival - self.clock()))
                 continue
-            self.step_cycle()
+            self.step_quantum()
             if not self.active and self.queue and self.queue[0].arrival <= self.clock():
                 raise RuntimeError("a queued request cannot be admitted")
         return self.results
 
     def latency(self) -> dict:
-        """Time from arrival to retirement over the served requests."""
+        """Time from arrival to retirement over the served requests, and time
+        from arrival to the periodic steady state over those whose detector
+        fired."""
         t = [r.t_done - r.t_arrival for r in self.results]
+        ss = [r.t_done - r.t_arrival for r in self.results if r.steady]
         return {"p50_s": percentile(t, 50), "p99_s": percentile(t, 99), "served": len(t),
-                "steady": sum(r.steady for r in self.results)}
+                "steady": len(ss), "ss_p50_s": percentile(ss, 50), "ss_p99_s": percentile(ss, 99)}

@@ -5,8 +5,8 @@ area and macro-particle weight that normalise them, and the tabulated cross
 sections.  It contains none of the PIC-MCC arithmetic (no push, no field solve,
 no collision sampling); both implementations receive these numbers as inputs.
 """
-from .configs import WORKLOADS, Workload, sweep, workload
+from .configs import WORKLOADS, Workload, served_stream, sweep, workload
 from .xsec import CHANNELS, N_CHANNELS, N_POINTS, energy_grid, build_tables
 
-__all__ = ["WORKLOADS", "Workload", "sweep", "workload", "CHANNELS", "N_CHANNELS",
+__all__ = ["WORKLOADS", "Workload", "served_stream", "sweep", "workload", "CHANNELS", "N_CHANNELS",
            "N_POINTS", "energy_grid", "build_tables"]

@@ -116,3 +116,22 @@ def sweep(count: int = 64, seed: int = 705049504) -> list:
                       sort_every=10, coulomb_every=10, seed=seed + 1 + i)
         out.append(wl.resolved())
     return out
+
+
+def served_stream(count: int = 32, seed: int = 705049700) -> list:
+    """Requests of the served stream: small discharges that reach the
+    periodic steady state within about a hundred rf cycles -- 4 cm, 128
+    cells, 13.56 MHz, dt = T_rf/1000, the small discharge's load (10k e, 2k
+    O-, 10k O2+), with U ~ U[300, 400] V and p ~ U[15, 25] Pa, sort and
+    Coulomb every 10 steps.  (The batched sweep's discharges need of the order
+    of 10^3 rf cycles of 4000 steps each, minutes to hours per request, so a
+    stream of them cannot be run to steady state here.)  Seeded."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    base = WORKLOADS["small"]
+    out = []
+    for i in range(count):
+        U = float(rng.uniform(300.0, 400.0))
+        p = float(rng.uniform(15.0, 25.0))
+        out.append(replace(base, name=f"served{i}", voltage_V=U, pressure_Pa=p, seed=seed + 1 + i).resolved())
+    return out

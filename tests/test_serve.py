@@ -48,7 +48,8 @@ class FakeDischarge:
 
     def step(self, n):
         assert not self.closed
-        self.cycles += n // self.wl.steps_per_period
+        self.steps = getattr(self, "steps", 0) + n
+        self.cycles = self.steps // self.wl.steps_per_period
 
     def moments(self):
         n = self.wl.n_cells
@@ -103,6 +104,40 @@ def test_server_admits_under_budget_and_refills_freed_slots():
         assert r.t_arrival <= r.t_admit <= r.t_done
     lat = s.latency()
     assert lat["served"] == 6 and lat["steady"] == 6 and lat["p50_s"] <= lat["p99_s"]
+    assert lat["ss_p50_s"] <= lat["ss_p99_s"]
+
+
+def test_server_admits_arrivals_at_launch_period_boundaries():
+    """Discharges advance one launch period (20 steps here) per round; a
+    request arriving mid-cycle joins at the next period boundary, and every
+    discharge's detector sees its own rf cycles."""
+    base = workload("small")                      # sort and Coulomb every 10 steps: period 20
+    M = base.steps_per_period
+    now = [0.0]
+
+    def clock():
+        return now[0]
+
+    steps_seen = []
+
+    def step_batch(ds, n):
+        steps_seen.append((n, [getattr(d, "steps", 0) for d in ds]))
+        fake_step_batch(ds, n)
+        now[0] += n                               # one time unit per step
+
+    s = Server(tables=(None, None, None), budget_bytes=10 * bytes_needed(base, "fp32"), backend=FakeDischarge,
+               step_batch=step_batch, clock=clock)
+    s.submit(Request(0, base, max_cycles=3, window=1, tol=0.0, arrival=0.0))
+    s.submit(Request(1, dataclasses.replace(base, seed=base.seed + 1), max_cycles=2, window=1, tol=0.0,
+                     arrival=M + 30.5))
+    res = {r.rid: r for r in s.run()}
+    assert all(n == 20 for n, _ in steps_seen)
+    # request 1 arrived 30.5 steps into request 0's second cycle: admitted at the next boundary (step 1040)
+    assert res[1].t_admit == M + 40
+    for _, counts in steps_seen:
+        assert all(c % 20 == 0 for c in counts)
+    assert res[0].cycles == 3 and res[1].cycles == 2
+    assert res[1].t_done == res[1].t_admit + 2 * M
 
 
 def test_server_rejects_mismatched_periods_and_oversized_requests():
