@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("eedf_bins", C.c_int32), ("eedf_emax_eV", C.c_double), ("fneg_xbins", C.c_int32),
         ("fneg_ebins", C.c_int32), ("fneg_emax_eV", C.c_double), ("coulomb_every", C.c_int32),
         ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32), ("field_off", C.c_int32),
+        ("dsmc", C.c_int32),
     ]
 
 
@@ -150,6 +151,7 @@ class Oracle:
         p.coulomb_log = wl.coulomb_log
         p.coulomb_inter = 1 if getattr(wl, "coulomb_inter", False) else 0
         p.field_off = 1 if field_off else 0
+        p.dsmc = 1 if getattr(wl, "dsmc", False) else 0
         self.params = p
         self.eedf_bins = eedf_bins
         self.nf = fneg_xbins * fneg_ebins

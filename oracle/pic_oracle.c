@@ -280,6 +280,11 @@ struct or_ctx {
   double PG[NCH];        /* tau * n_target for gas channels */
   double PGtot[3];
   double KP[NCH];        /* tau * M_j * W / (A dx) for partner channels */
+  /* per-cell collision list (dsmc): tau = sort_every dt for every type */
+  double PGl[NCH];       /* tau * n_target for gas channels */
+  double Bl[16];         /* bound of Eq. (1) for gas type (4 + t): PGl * max sigma g */
+  double KPl;            /* tau * W / (A dx): Eq. (1) per partner particle of the cell and unit sigma g */
+  double KMl[NCH];       /* KPl * M_j for partner channels */
   double cphi, cE;
   real cc_coul[3], cc_coul_half[3]; /* Eq. (2) prefactor per particle in the cell */
   real cc_inter[3];                  /* the same for the pairs (e, O-), (e, O2+), (O-, O2+) */
@@ -320,6 +325,22 @@ static const int n_part_ch[3] = {2, 1, 0};
 static const int gas_ch_e[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
 static const int gas_ch_n[] = {14, 15, 16};
 static const int gas_ch_p[] = {18};
+
+/* the collision list of Table I in order, type (4 + t) of the per-cell scheme */
+typedef struct {
+  int sp, n, ch[4];  /* test species, gas channels (n = 0: partner type with channel ch[0]) */
+} ltype;
+
+static const ltype LIST[16] = {
+    {SP_E, 1, {0}},  {SP_N, 1, {14}}, {SP_P, 1, {18}}, {SP_E, 4, {1, 2, 3, 4}}, {SP_E, 1, {5}},
+    {SP_E, 1, {6}},  {SP_E, 1, {7}},  {SP_E, 1, {8}},  {SP_E, 1, {9}},          {SP_E, 0, {12}},
+    {SP_N, 0, {17}}, {SP_E, 1, {10}}, {SP_N, 1, {15}}, {SP_N, 1, {16}},         {SP_E, 1, {11}},
+    {SP_E, 0, {13}}};
+
+/* random streams of type (4 + t): decision, gas molecule, scattering angles */
+#define LK_DEC(t) (32u + 3u * (uint32_t)(t))
+#define LK_GAS(t) (33u + 3u * (uint32_t)(t))
+#define LK_ANG(t) (34u + 3u * (uint32_t)(t))
 
 static void gas_channels(int s, const int** list, int* n) {
   if (s == SP_E) { *list = gas_ch_e; *n = 12; }
@@ -490,7 +511,8 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
   *err = OR_OK;
   if (p->n_cells < 4 || p->gap_m <= 0 || p->area_m2 <= 0 || p->weight <= 0 || p->steps_per_period < 1 ||
       p->ion_subcycle < 1 || p->sort_every < 1 || p->frequency_Hz <= 0 || p->coulomb_every < 0 ||
-      (p->coulomb_every > 0 && (p->coulomb_every % p->sort_every != 0 || !(p->coulomb_log > 0)))) {
+      (p->coulomb_every > 0 && (p->coulomb_every % p->sort_every != 0 || !(p->coulomb_log > 0))) ||
+      p->dsmc < 0 || p->dsmc > 1 || (p->dsmc && p->sort_every % p->ion_subcycle != 0)) {
     *err = OR_EINVAL;
     return NULL;
   }
@@ -576,6 +598,21 @@ or_ctx* or_create(const or_params* p, const double* sigma, const double* thr, co
     c->PGtot[SP_E] = c->PG[0] * c->M_gas[SP_E];
     c->PGtot[SP_N] = c->PG[14] * c->M_gas[SP_N] + c->PG[16] * c->M_ad;
     c->PGtot[SP_P] = c->PG[18] * c->M_gas[SP_P];
+    if (p->dsmc) {
+      double tl = c->dt * (double)p->sort_every;
+      for (int j = 0; j < NCH; j++) {
+        if (partner_of[j] >= 0) continue;
+        c->PGl[j] = (j == 16) ? (tl * p->metastable_frac) * c->ngas : tl * c->ngas;
+      }
+      c->KPl = (tl * p->weight) / (p->area_m2 * c->dx);
+      for (int j = 0; j < NCH; j++)
+        if (partner_of[j] >= 0) c->KMl[j] = c->KPl * c->M_ch[j];
+      for (int t = 0; t < 16; t++) {
+        if (LIST[t].n == 0) continue;
+        c->Bl[t] = c->PGl[LIST[t].ch[0]] * bound_M(sigma, LIST[t].ch, LIST[t].n, mu[LIST[t].sp]);
+        if (c->Bl[t] > 1.0) { *err = OR_EINVAL; or_destroy(c); return NULL; }
+      }
+    }
   }
   /* Eq. (2) with eps0^2 (Takizuka-Abe): <tan^2(chi/2)> = q^4 n lnL t_c2 / (8 pi eps0^2 mu^2 u^3),
      mu = m/2, n = W N_cell / (A dx), t_c2 = coulomb_every dt */
@@ -763,9 +800,10 @@ static void ee_elastic(real va[3], real vb[3], const real n[3]) {
 }
 
 /* collision with a gas molecule drawn from the Maxwellian (Sec. III A/B/C) */
-static void gas_event(or_ctx* c, int s, int j, part* p, const real vt[3], real g, real Erel, uint32_t n) {
+static void gas_event(or_ctx* c, int s, int j, part* p, const real vt[3], real g, real Erel, uint32_t n,
+                      uint32_t kr) {
   uint32_t w[4];
-  rng(c->P.seed, p->id, n, 2, w);
+  rng(c->P.seed, p->id, n, kr, w);
   real n1[3], n2[3];
   iso_dir(w[0], w[1], n1);
   iso_dir(w[2], w[3], n2);
@@ -854,7 +892,7 @@ static void mcc(or_ctx* c, int s, int64_t idx, part* p, uint32_t n, double pmax)
     real sg = 0;
     if (Erel >= c->thr[j]) sg = sigma_at(c, j, Erel) * g;
     cum = cum + c->PG[j] * (double)sg;
-    if (U < cum) { gas_event(c, s, j, p, vt, g, Erel, n); return; }
+    if (U < cum) { gas_event(c, s, j, p, vt, g, Erel, n, 2); return; }
   }
 }
 
@@ -881,8 +919,10 @@ static void push_species(or_ctx* c, int s, uint32_t n) {
     p->cell = cell;
     if (cell < 0) { c->absorbed[0][s]++; p->alive = 0; continue; }
     if (cell >= N) { c->absorbed[1][s]++; p->alive = 0; continue; }
-    mcc(c, s, i, p, n, pmax);
-    if (!p->alive) continue;
+    if (!c->P.dsmc) {
+      mcc(c, s, i, p, n, pmax);
+      if (!p->alive) continue;
+    }
     if (s == SP_E && cell == cmid && c->P.eedf_bins > 0) {
       real e2 = (p->v[0] * p->v[0] + p->v[1] * p->v[1]) + p->v[2] * p->v[2];
       real Ek = c->hme * e2;
@@ -910,6 +950,42 @@ static uint64_t pick_key(uint64_t seed, uint64_t id_p, uint64_t id_t, uint32_t n
   uint32_t w[4];
   or_philox(ctr, key, w);
   return ((uint64_t)(w[0] >> 8) << 40) | (id_p & ID_MASK);
+}
+
+/* (19): inelastic e-O- collision of test electron T and partner O- P: the O-
+   splits into O + e (loss dE of Eq. (5)), the two electrons scatter
+   elastically; directions from stream kr of T */
+static void impact_detach(or_ctx* c, part* T, part* P, uint32_t n, uint32_t kr) {
+  const int j = 13;
+  real a = c->a_c[j], b = c->b_c[j];
+  real gx = T->v[0] - P->v[0], gy = T->v[1] - P->v[1], gz = T->v[2] - P->v[2];
+  real g2 = (gx * gx + gy * gy) + gz * gz;
+  real Erel = c->hmu_c[j] * g2;
+  uint32_t w[4];
+  rng(c->P.seed, T->id, n, kr, w);
+  real n1[3], n2[3];
+  iso_dir(w[0], w[1], n1);
+  iso_dir(w[2], w[3], n2);
+  real vc[3], ve[3], vn[3], vo[3];
+  for (int d = 0; d < 3; d++) vc[d] = b * T->v[d] + a * P->v[d];
+  real Ep = Erel - c->loss[j];
+  real gp = RSQRT(Ep * c->c2e_c[j]);
+  real ag = a * gp, bg = b * gp;
+  double pb[3], pa[3];
+  double keb = ke(ME, T->v) + ke(c->mass[SP_N], P->v);
+  for (int d = 0; d < 3; d++) {
+    pb[d] = ME * (double)T->v[d] + c->mass[SP_N] * (double)P->v[d];
+    ve[d] = vc[d] + ag * n1[d];
+    vo[d] = vc[d] - bg * n1[d];
+    vn[d] = vo[d];
+  }
+  ee_elastic(ve, vn, n2);
+  for (int d = 0; d < 3; d++) T->v[d] = ve[d];
+  P->alive = 0;
+  add_birth(c, SP_E, T->id, 0, P->cell, P->off, vn);
+  double kea = ke(ME, ve) + ke(ME, vn) + ke(c->mass[SP_N] - ME, vo);
+  for (int d = 0; d < 3; d++) pa[d] = ME * (double)ve[d] + ME * (double)vn[d] + (c->mass[SP_N] - ME) * (double)vo[d];
+  log_event(c, j, SP_E, keb, kea, pb, pa, 0, 0);
 }
 
 /* partner reactions: pick, acceptance, claims (Sec. III C, Eq. (1)) */
@@ -975,38 +1051,140 @@ static void claims(or_ctx* c, uint32_t n) {
       c->nacc++;
       c->events[j]++;
       if (j == 12 || j == 17) { T->alive = 0; P->alive = 0; continue; }
-      /* (19): inelastic e-O- collision, O- split into O + e, e-e elastic */
-      real a = c->a_c[j], b = c->b_c[j];
-      real gx = T->v[0] - P->v[0], gy = T->v[1] - P->v[1], gz = T->v[2] - P->v[2];
-      real g2 = (gx * gx + gy * gy) + gz * gz;
-      real Erel = c->hmu_c[j] * g2;
-      uint32_t w[4];
-      rng(c->P.seed, T->id, n, 2, w);
-      real n1[3], n2[3];
-      iso_dir(w[0], w[1], n1);
-      iso_dir(w[2], w[3], n2);
-      real vc[3], ve[3], vn[3], vo[3];
-      for (int d = 0; d < 3; d++) vc[d] = b * T->v[d] + a * P->v[d];
-      real Ep = Erel - c->loss[j];
-      real gp = RSQRT(Ep * c->c2e_c[j]);
-      real ag = a * gp, bg = b * gp;
-      double pb[3], pa[3];
-      double keb = ke(ME, T->v) + ke(c->mass[SP_N], P->v);
-      for (int d = 0; d < 3; d++) {
-        pb[d] = ME * (double)T->v[d] + c->mass[SP_N] * (double)P->v[d];
-        ve[d] = vc[d] + ag * n1[d];
-        vo[d] = vc[d] - bg * n1[d];
-        vn[d] = vo[d];
-      }
-      ee_elastic(ve, vn, n2);
-      for (int d = 0; d < 3; d++) T->v[d] = ve[d];
-      P->alive = 0;
-      add_birth(c, SP_E, T->id, 0, P->cell, P->off, vn);
-      double kea = ke(ME, ve) + ke(ME, vn) + ke(c->mass[SP_N] - ME, vo);
-      for (int d = 0; d < 3; d++) pa[d] = ME * (double)ve[d] + ME * (double)vn[d] + (c->mass[SP_N] - ME) * (double)vo[d];
-      log_event(c, j, SP_E, keb, kea, pb, pa, 0, 0);
+      impact_detach(c, T, P, n, 2);
     }
   }
+}
+
+/* ----------------------------------------------------------------------- */
+/* the per-cell collision list of Sec. II (test switch dsmc = 1): after the */
+/* sort every sort_every steps, the particles of each cell go through the   */
+/* collision types (4)-(19) of Table I in the table's order, type (4 + t)   */
+/* with the probability of Eq. (1), P = n_j sigma_j u tau, and tau =        */
+/* sort_every dt for all of them.  The products of a type are placed, with  */
+/* canonical ids, before the next type starts and take part in the later    */
+/* ones; the partner densities n_j of a type are those at its start.        */
+/* Readings: one decision per particle and type (the four vibrational       */
+/* levels of (7) form one type, the level chosen with the same uniform); a  */
+/* gas molecule is drawn for each decision; a simulated partner is one      */
+/* particle of the cell chosen by a hash of the two ids; when several test  */
+/* particles accept the same partner, the one with the smallest id collides.*/
+/* A uniform at or above the type's largest probability cannot collide, so  */
+/* no target is drawn for it (the draws are counter-based: this changes no  */
+/* other draw).                                                             */
+/* ----------------------------------------------------------------------- */
+static int commit_births(or_ctx* c);
+
+static void list_gas_type(or_ctx* c, int t, uint32_t n) {
+  const ltype* L = &LIST[t];
+  int s = L->sp;
+  store* S = &c->st[s];
+  for (int64_t i = 0; i < S->n; i++) {
+    part* p = &S->a[i];
+    if (!p->alive) continue;
+    uint32_t w[4];
+    rng(c->P.seed, p->id, n, LK_DEC(t), w);
+    double U = unif52(w[0], w[1]);
+    if (!(U < c->Bl[t])) continue;
+    uint32_t u[4];
+    rng(c->P.seed, p->id, n, LK_GAS(t), u);
+    real r1 = bm_radius(unif(u[0])), a1 = unif(u[1]);
+    real r2 = bm_radius(unif(u[2])), a2 = unif(u[3]);
+    real vt[3];
+    vt[0] = c->vthg * (r1 * cos2pi(a1));
+    vt[1] = c->vthg * (r1 * sin2pi(a1));
+    vt[2] = c->vthg * (r2 * cos2pi(a2));
+    real gx = p->v[0] - vt[0], gy = p->v[1] - vt[1], gz = p->v[2] - vt[2];
+    real g2 = (gx * gx + gy * gy) + gz * gz;
+    real g = RSQRT(g2);
+    real Erel = c->hmu_g[s] * g2;
+    if (Erel >= (real)16384) c->tophits++;
+    double cum = 0.0;
+    for (int q = 0; q < L->n; q++) {
+      int j = L->ch[q];
+      real sg = 0;
+      if (Erel >= c->thr[j]) sg = sigma_at(c, j, Erel) * g;
+      cum = cum + c->PGl[j] * (double)sg;
+      if (U < cum) { gas_event(c, s, j, p, vt, g, Erel, n, LK_ANG(t)); break; }
+    }
+  }
+}
+
+static int list_partner_type(or_ctx* c, int t, uint32_t n) {
+  int j = LIST[t].ch[0];
+  int s = LIST[t].sp, tg = partner_of[j];
+  store* S = &c->st[s];
+  store* P = &c->st[tg];
+  int64_t* cnt = (int64_t*)calloc((size_t)c->N, sizeof(int64_t));
+  for (int64_t i = 0; i < P->n; i++)
+    if (P->a[i].alive) cnt[P->a[i].cell]++;
+  c->nreq_step = 0;
+  int rc = OR_OK;
+  for (int64_t i = 0; i < S->n; i++) {
+    part* T = &S->a[i];
+    if (!T->alive) continue;
+    double Nt = (double)cnt[T->cell];
+    if (Nt * c->KMl[j] > 1.0) { rc = OR_EGUARD; break; }
+    uint32_t w[4];
+    rng(c->P.seed, T->id, n, LK_DEC(t), w);
+    double U = unif52(w[0], w[1]);
+    if (!(U < Nt * c->KMl[j])) continue;
+    uint64_t best = UINT64_MAX;
+    int64_t bi = -1;
+    for (int64_t k = 0; k < P->n; k++) {
+      if (!P->a[k].alive || P->a[k].cell != T->cell) continue;
+      uint64_t key = pick_key(c->P.seed, P->a[k].id, T->id, n);
+      if (key < best) { best = key; bi = k; }
+    }
+    c->nreq++;
+    part* Q = &P->a[bi];
+    real gx = T->v[0] - Q->v[0], gy = T->v[1] - Q->v[1], gz = T->v[2] - Q->v[2];
+    real g2 = (gx * gx + gy * gy) + gz * gz;
+    real g = RSQRT(g2);
+    real Erel = c->hmu_c[j] * g2;
+    real sg = 0;
+    if (Erel >= c->thr[j]) sg = sigma_at(c, j, Erel) * g;
+    if (!(U < (Nt * c->KPl) * (double)sg)) continue;
+    add_request(c, s, i, T, j, 0);
+    c->req[c->nreq_step - 1].partner = bi;
+  }
+  free(cnt);
+  if (rc) return rc;
+  /* a partner accepted by several test particles collides with the smallest id */
+  int64_t R = c->nreq_step;
+  for (int64_t r = 0; r < R; r++) {
+    request* q = &c->req[r];
+    q->accepted = 1;
+    for (int64_t r2 = 0; r2 < R; r2++)
+      if (c->req[r2].partner == q->partner && c->req[r2].id < q->id) q->accepted = 0;
+  }
+  for (int64_t r = 0; r < R; r++) {
+    request* q = &c->req[r];
+    if (!q->accepted) continue;
+    part* T = &S->a[q->idx];
+    part* Q = &P->a[q->partner];
+    c->nacc++;
+    c->events[j]++;
+    if (j == 13) impact_detach(c, T, Q, n, LK_ANG(t));
+    else { T->alive = 0; Q->alive = 0; }
+  }
+  c->nreq_step = 0;
+  return OR_OK;
+}
+
+static int list_pass(or_ctx* c, uint32_t n) {
+  for (int t = 0; t < 16; t++) {
+    if (LIST[t].n > 0) list_gas_type(c, t, n);
+    else {
+      int rc = list_partner_type(c, t, n);
+      if (rc) return rc;
+    }
+    if (c->nbir > 0) {
+      int rc = commit_births(c);
+      if (rc) return rc;
+    }
+  }
+  return OR_OK;
 }
 
 /* ----------------------------------------------------------------------- */
@@ -1261,7 +1439,7 @@ static int one_step(or_ctx* c) {
   for (int i = 0; i <= N; i++) c->phiacc[i] += c->phi[i];
   for (int s = 0; s < 3; s++) {
     if (s != SP_E && !ion) continue;
-    if (pmax_of(c, s) > 1.0) return OR_EGUARD;
+    if (!c->P.dsmc && pmax_of(c, s) > 1.0) return OR_EGUARD;
   }
   c->nreq_step = 0;
   c->nbir = 0;
@@ -1274,7 +1452,14 @@ static int one_step(or_ctx* c) {
   if (c->nanflag) return OR_EGUARD;
   int rc = commit_births(c);
   if (rc) return rc;
-  if ((c->step + 1) % c->P.sort_every == 0) do_sort(c);
+  if ((c->step + 1) % c->P.sort_every == 0) {
+    do_sort(c);
+    if (c->P.dsmc) {
+      rc = list_pass(c, n);
+      if (rc) return rc;
+      do_sort(c);
+    }
+  }
   if (c->P.coulomb_every > 0 && (c->step + 1) % c->P.coulomb_every == 0) {
     coulomb(c, n);
     if (c->P.coulomb_inter) coulomb_inter(c, n);

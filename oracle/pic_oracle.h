@@ -43,6 +43,9 @@ typedef struct {
   int32_t coulomb_inter;      /* 1: inter-species Coulomb collisions after the intra-species ones */
   int32_t field_off;          /* test switch, 1: the particles' charge does not enter the field
                                  (rate pins at weights whose self field would swamp the step) */
+  int32_t dsmc;               /* 1: collisions (4)-(19) as the per-cell list of Sec. II every sort_every
+                                 steps (tau = sort_every dt) instead of null-collision Monte Carlo
+                                 every step; sort_every a multiple of ion_subcycle */
 } or_params;
 
 typedef struct or_ctx or_ctx;

@@ -55,6 +55,7 @@ class Workload:
     coulomb_every: int = 0       # intra-species Coulomb collisions every n2 steps (0: off)
     coulomb_log: float = 10.0
     coulomb_inter: bool = False  # inter-species Coulomb collisions as well
+    dsmc: bool = False           # collisions (4)-(19) as the per-cell list of Sec. II every sort_every steps
     seed: int = 705049500
     area_m2: float = field(default_factory=debye_area)
     weight: float = 0.0      # 0 -> n_res * A * L / N_e(0)
