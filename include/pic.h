@@ -94,6 +94,19 @@ typedef struct {
                                  (O-,O2+) collide in each cell (binary model of Takizuka and Abe,
                                  Eq. (2) with the reduced mass and the lower of the two densities;
                                  an extension: Sec. III names only like-species collisions) */
+  int32_t dsmc;               /* 0: null-collision Monte Carlo of (4)-(19) in every push (tau = the
+                                 species' push interval); 1: the per-cell collision list of Sec. II
+                                 instead: every sort_every steps, after the sort, the particles of
+                                 each cell go through the types (4)-(19) of Table I in order, each
+                                 with P = n_j sigma_j u tau of Eq. (1), tau = sort_every dt; products
+                                 of a type take part in the later ones; a partner type uses the
+                                 populations at its start (one partner per test particle, chosen by
+                                 a hash of the two ids; the smallest test id wins a partner).
+                                 Requires sort_every to be a multiple of ion_subcycle and every gas
+                                 type's tau n max(sigma g) <= 1 (else PIC_EINVAL); a partner type
+                                 whose N_t(c) tau W max(sigma g) / (A dx) exceeds 1 in a cell with
+                                 test particles raises the guard.  Not batched: pic_step_batch
+                                 steps such a discharge alone */
 } pic_gas;
 
 /*

@@ -40,7 +40,7 @@ class Gas(C.Structure):
     _fields_ = [
         ("T_gas_K", C.c_double), ("metastable_frac", C.c_double), ("sigma_m2", C.POINTER(C.c_double)),
         ("threshold_eV", C.POINTER(C.c_double)), ("loss_eV", C.POINTER(C.c_double)),
-        ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32),
+        ("coulomb_log", C.c_double), ("coulomb_inter", C.c_int32), ("dsmc", C.c_int32),
     ]
 
 
@@ -134,6 +134,7 @@ class Discharge:
         gas.loss_eV = _p(self._loss, C.c_double)
         gas.coulomb_log = getattr(wl, "coulomb_log", 0.0)
         gas.coulomb_inter = int(bool(getattr(wl, "coulomb_inter", False)))
+        gas.dsmc = int(bool(getattr(wl, "dsmc", False)))
         self.h = C.c_void_p()
         rc = self.L.pic_create(C.byref(g), C.byref(gas), wl.voltage_V, wl.frequency_Hz, wl.pressure_Pa,
                                C.byref(self.h))

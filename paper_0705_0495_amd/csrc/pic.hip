@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "pic_kernels.hpp"
+#include "pic_list.hpp"
 
 using namespace pic;
 
@@ -148,6 +149,8 @@ struct Impl : Base {
   int tab_total = 0;  // values of the compact gas-channel copies (Dev::sigc)
   bool graphs = false;                // replay captured step sequences
   hipGraphExec_t gexec = nullptr;     // period() steps from a step count divisible by period()
+  bool list = false;                  // collisions (4)-(19) as the per-cell list (pic_gas::dsmc)
+  ListK LK;
 
   explicit Impl(pic_ctx* ctx) : c(ctx) { memset(&D, 0, sizeof(D)); memset(&C, 0, sizeof(C)); }
   ~Impl() override {
@@ -283,6 +286,7 @@ struct Impl : Base {
     // partner channels 12 (e, O2+), 13 (e, O-), 17 (O-, O2+): the slot of Eq. (1)
     // per partner particle of the cell is tau M_j W / (A dx), W real particles each
     const int pch[3] = {12, 13, 17}, ps[3] = {0, 0, 1}, pt[3] = {2, 1, 2};
+    double Mpart[3];
     const double* sig = c->sigma.data();
     for (int q = 0; q < 3; q++) {
       const double ms = mass[ps[q]], mt = mass[pt[q]];
@@ -295,6 +299,7 @@ struct Impl : Base {
       const double Mj = bound_sum(sig, one, 1, mu);
       C.Mr_c[q] = (R)Mj;
       C.KP[q] = ((tau[ps[q]] * Mj) * G.weight) / (G.area_m2 * dx);
+      Mpart[q] = Mj;
     }
     C.ddf = (R)std::sqrt((0.1 * mass[1]) / ME);
     C.adf = (R)std::sqrt(mu_g[1] / ME);
@@ -342,6 +347,27 @@ struct Impl : Base {
     C.PGtot[0] = C.PG[0] * Me;
     C.PGtot[1] = C.PG[14] * Mn + C.PG[16] * Mad;
     C.PGtot[2] = C.PG[18] * Mp;
+    // the per-cell collision list of Sec. II: every type (4)-(19) with tau =
+    // sort_every dt, once per sort; the null-collision test of the push is off
+    list = c->gas.dsmc != 0;
+    memset(&LK, 0, sizeof(LK));
+    if (list) {
+      const double tl = dt * (double)G.sort_every;
+      for (int j = 0; j < NCH; j++) {
+        if (j == 12 || j == 13 || j == 17) continue;
+        LK.PGl[j] = (j == 16) ? (tl * c->gas.metastable_frac) * ngas : tl * ngas;
+      }
+      LK.KPl = (tl * G.weight) / (G.area_m2 * dx);
+      for (int q = 0; q < 3; q++) LK.KM[q] = LK.KPl * Mpart[q];
+      for (int t = 0; t < LIST_N; t++) {
+        if (LIST_NCH[t] == 0) continue;
+        int ch[4];
+        for (int q = 0; q < LIST_NCH[t]; q++) ch[q] = LIST_CH0[t] + q;
+        LK.B[t] = LK.PGl[LIST_CH0[t]] * bound_sum(sig, ch, LIST_NCH[t], mu_g[LIST_SP[t]]);
+      }
+      for (int s = 0; s < 3; s++) C.PGtot[s] = 0.0;
+      for (int q = 0; q < 3; q++) C.KP[q] = 0.0;
+    }
     C.cphi = ((dx * QE) * G.weight) / ((EPS0 * 16777216.0) * G.area_m2);
     C.cE = (QE * G.weight) / ((EPS0 * 16777216.0) * G.area_m2);
     C.invdx = 1.0 / dx;
@@ -441,6 +467,14 @@ struct Impl : Base {
     if ((rc = alloc(&D.ncand, 3))) return rc;
     D.req_cap = REQ_CAP;
     if ((rc = alloc(&D.req, (size_t)D.req_cap))) return rc;
+    if (list) {
+      for (int t = 0; t < LIST_N; t++)
+        if (LIST_NCH[t] > 0 && LK.B[t] > 1.0)
+          return fail(c, PIC_EINVAL, "collision list: tau n sigma g of type (" + std::to_string(4 + t) +
+                                         ") can exceed 1; sort every fewer steps");
+      D.lreq_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(REQ_CAP, totcap / 64), 1 << 24);
+      if ((rc = alloc(&D.lreq, (size_t)D.lreq_cap))) return rc;
+    }
     if ((rc = alloc(&D.nreq, 1))) return rc;
     if ((rc = alloc(&D.ctr, 1))) return rc;
     if ((rc = alloc(&D.Qcur, 3 * (size_t)(N + 1)))) return rc;
@@ -618,6 +652,54 @@ struct Impl : Base {
     return 0;
   }
 
+  // the device copy of D at the current buffer parity
+  const Dev<R>* dpar() const { return dD + (D.st[0].cell == dev_parity0_cell ? 0 : 1); }
+
+  // the per-cell collision list after the sort of this step's end: the types
+  // in the order of Table I, births placed after each type that makes them,
+  // the sort repeated before impact detachment (19) (its O- partners include
+  // those born in (15)) and at the end
+  void list_partner_kernels(int t, int grid) {
+    const Dev<R>* dp = dpar();
+    const int gc = 64;
+    if (t == 9) {
+      hipLaunchKernelGGL((k_list_pick<R, 9>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+      hipLaunchKernelGGL((k_list_claim<R, 9>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dp);
+      hipLaunchKernelGGL((k_list_apply<R, 9>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dC, dp);
+    } else if (t == 10) {
+      hipLaunchKernelGGL((k_list_pick<R, 10>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+      hipLaunchKernelGGL((k_list_claim<R, 10>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dp);
+      hipLaunchKernelGGL((k_list_apply<R, 10>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dC, dp);
+    } else {
+      hipLaunchKernelGGL((k_list_pick<R, 15>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+      hipLaunchKernelGGL((k_list_claim<R, 15>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dp);
+      hipLaunchKernelGGL((k_list_apply<R, 15>), dim3(gc), dim3(LIST_TPB), 0, c->stream, dC, dp);
+    }
+    hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
+  }
+
+  int list_pass() {
+    const int grid = std::max(1, ncu * 8);
+    const Dev<R>* dp = dpar();
+    hipLaunchKernelGGL(k_list_scatter<R>, dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+    list_partner_kernels(9, grid);
+    list_partner_kernels(10, grid);
+    hipLaunchKernelGGL((k_list_gas<R, 11>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+    hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
+    hipLaunchKernelGGL((k_list_gas<R, 12>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+    hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
+    hipLaunchKernelGGL((k_list_gas<R, 13>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+    hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
+    hipLaunchKernelGGL((k_list_gas<R, 14>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
+    hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
+    HIPCHK(c, hipGetLastError());
+    int rc = sort();
+    if (rc) return rc;
+    list_partner_kernels(15, grid);
+    HIPCHK(c, hipGetLastError());
+    return sort();
+  }
+
   template <class SH>
   void launch_push_sh(const Dev<R>* dpar) {
     if (elds) hipLaunchKernelGGL((k_push<R, true, SH>), dim3(grid_push), dim3(SH::TPB), 0, c->stream, dC, dpar);
@@ -655,6 +737,7 @@ struct Impl : Base {
       if (sort_now) {
         int rc = sort();
         if (rc) return rc;
+        if (list && (rc = list_pass())) return rc;
         const int ce = c->G.coulomb_every;
         if (ce > 0 && nstep % ce == 0) {
           HIPCHK(c, launch_coulomb(C, D, ncu, c->stream));
@@ -977,6 +1060,8 @@ bool batch_compatible(pic_ctx* const* ctx, int n) {
     const pic_geometry& G = ctx[i]->G;
     if (G.precision != G0.precision || G.sort_every != G0.sort_every || G.coulomb_every != G0.coulomb_every)
       return false;
+    // the per-cell collision list runs per discharge
+    if (ctx[i]->gas.dsmc) return false;
     // the launch sequence is decided once for the batch: every context must
     // stand at the same phase of it (the steps themselves may differ)
     const int64_t P = ctx[0]->impl->chunk_period();
@@ -1054,7 +1139,8 @@ int pic_create(const pic_geometry* g, const pic_gas* gas, double voltage_V, doub
       (int64_t)g->fneg_xbins * g->fneg_ebins > FNEG_MAX || (g->eedf_bins > 0 && !(g->eedf_emax_eV > 0)) ||
       (g->fneg_ebins > 0 && !(g->fneg_emax_eV > 0)) || g->coulomb_every < 0 ||
       (g->coulomb_every > 0 && (g->coulomb_every % g->sort_every != 0 || !(gas->coulomb_log > 0))) ||
-      gas->coulomb_inter < 0 || gas->coulomb_inter > 1)
+      gas->coulomb_inter < 0 || gas->coulomb_inter > 1 || gas->dsmc < 0 || gas->dsmc > 1 ||
+      (gas->dsmc && g->sort_every % g->ion_subcycle != 0))
     return PIC_EINVAL;
   for (int s = 0; s < 3; s++)
     if (g->n_init[s] < 0 || g->n_init[s] > ((int64_t)1 << 30) - 65536 || g->T_init_eV[s] < 0) return PIC_EINVAL;

@@ -204,6 +204,8 @@ struct Dev {
   int32_t* coul_big;  // [3 Nc] their (species, cell) indices
   int32_t* ncl;     // cells listed for the largest LDS class in this pass
   int32_t* clist;   // [3 Nc] their (species, cell) indices
+  Request<R>* lreq; // accepted requests of one partner type of the per-cell collision list
+  int32_t lreq_cap;
 };
 
 // ---------------------------------------------------------------------------
@@ -757,8 +759,8 @@ __device__ __forceinline__ void diag_alive(const Consts<R>& C, DiagLds& G, int c
 // ---------------------------------------------------------------------------
 template <class R, int S>
 __device__ __forceinline__ bool gas_event(const Consts<R>& C, const Dev<R>& D, int j, int cell, R off, uint64_t id, R v[3],
-                          const R vt[3], R g, R Erel, uint32_t n) {
-  const uint4 w = rng(C, id, n, 2);
+                          const R vt[3], R g, R Erel, uint32_t n, uint32_t kr) {
+  const uint4 w = rng(C, id, n, kr);
   R n1[3], n2[3];
   iso_dir<R>(C, w.x, w.y, n1);
   iso_dir<R>(C, w.z, w.w, n2);
@@ -928,7 +930,7 @@ __device__ __forceinline__ void collide_apply(const Consts<R>& C, const Dev<R>& 
   }
   if (hit >= 0) {
     atomicAdd(&G.ev[hit], 1);
-    if (gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n)) {
+    if (gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n, 2)) {
       st.vx[slot] = v[0];
       st_yz(st, slot, v[1], v[2]);
     } else {
@@ -1175,8 +1177,12 @@ __device__ __forceinline__ TileCount push_tile(const Consts<R>& C, const Dev<R>&
       run_val = 0;
     }
     run_val += (1ull << 40) + (uint64_t)frac24(o);
-    const uint4 w = rng(C, id[q], n, 0);
-    if ((uint64_t)w.x < T0 && unif52(w.x, w.y) < pmax) {
+    bool cand = false;
+    if (T0 != 0) {
+      const uint4 w = rng(C, id[q], n, 0);
+      cand = (uint64_t)w.x < T0 && unif52(w.x, w.y) < pmax;
+    }
+    if (cand) {
       candmask |= 1 << q;
     } else if (S == 0) {
       if (cn == C.cmid) {
@@ -1472,6 +1478,44 @@ __device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int s
   st.cell[slot] = DEAD;
 }
 
+// (19): inelastic collision of test electron `slot` (id) with partner O- `p`:
+// the O- splits into O + e (loss dE of Eq. (5)), the two electrons scatter
+// elastically; directions from the electron's stream kr
+template <class R>
+__device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int p, uint64_t id, uint32_t n, uint32_t kr) {
+  const Store<R> es = D.st[0], ns = D.st[1];
+  R T[3], P[3];
+  T[0] = es.vx[slot];
+  ld_yz(es, slot, T[1], T[2]);
+  P[0] = ns.vx[p];
+  ld_yz(ns, p, P[1], P[2]);
+  const R a = C.a_c[1], b = C.b_c[1];
+  const R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
+  const R g2 = (gx * gx + gy * gy) + gz * gz;
+  const R Erel = C.hmu_c[1] * g2;
+  const uint4 w = rng(C, id, n, kr);
+  R n1[3], n2[3];
+  iso_dir<R>(C, w.x, w.y, n1);
+  iso_dir<R>(C, w.z, w.w, n2);
+  const R Ep = Erel - C.loss[13];
+  const R gp = Sqrt(Ep * C.c2e_c[1]);
+  const R ag = a * gp, bg = b * gp;
+  R ve[3], vn[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const R vc = b * T[d] + a * P[d];
+    ve[d] = vc + ag * n1[d];
+    vn[d] = vc - bg * n1[d];
+  }
+  ee_elastic<R>(ve, vn, n2);
+  es.vx[slot] = ve[0];
+  st_yz(es, slot, ve[1], ve[2]);
+  const int pc = ns.cell[p];
+  const R po = ns.off[p];
+  kill_particle(C, D, 1, p);
+  add_birth(C, D, 0, id, 0, pc, po, vn[0], vn[1], vn[2]);
+}
+
 struct ClaimLds {
   int32_t rpart[REQ_CAP];
   uint64_t rid[REQ_CAP];
@@ -1555,39 +1599,7 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
       kill_particle(C, D, 2, L.rpart[r]);
       continue;
     }
-    // (19): inelastic e-O- collision, O- split into O + e, e-e elastic
-    const Store<R> es = D.st[0], ns = D.st[1];
-    const int p = L.rpart[r];
-    R T[3], P[3];
-    T[0] = es.vx[q.slot];
-    ld_yz(es, q.slot, T[1], T[2]);
-    P[0] = ns.vx[p];
-    ld_yz(ns, p, P[1], P[2]);
-    const R a = C.a_c[1], b = C.b_c[1];
-    const R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
-    const R g2 = (gx * gx + gy * gy) + gz * gz;
-    const R Erel = C.hmu_c[1] * g2;
-    const uint4 w = rng(C, q.id, n, 2);
-    R n1[3], n2[3];
-    iso_dir<R>(C, w.x, w.y, n1);
-    iso_dir<R>(C, w.z, w.w, n2);
-    const R Ep = Erel - C.loss[13];
-    const R gp = Sqrt(Ep * C.c2e_c[1]);
-    const R ag = a * gp, bg = b * gp;
-    R ve[3], vn[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      const R vc = b * T[d] + a * P[d];
-      ve[d] = vc + ag * n1[d];
-      vn[d] = vc - bg * n1[d];
-    }
-    ee_elastic<R>(ve, vn, n2);
-    es.vx[q.slot] = ve[0];
-    st_yz(es, q.slot, ve[1], ve[2]);
-    const int pc = ns.cell[p];
-    const R po = ns.off[p];
-    kill_particle(C, D, 1, p);
-    add_birth(C, D, 0, q.id, 0, pc, po, vn[0], vn[1], vn[2]);
+    impact_detach(C, D, q.slot, L.rpart[r], q.id, n, 2);
   }
   __syncthreads();
   // stage 2: O- test particles (14); the O- must not have been taken by a
@@ -1734,6 +1746,28 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
   }
 }
 
+// after births_phase (one thread): the births join the store lengths and the
+// id counter; the birth and request lists are emptied
+template <class R>
+__device__ void close_births(const Dev<R>& D) {
+  int B = D.nbc[0];
+  if (B > D.nb_cap) B = D.nb_cap;
+  for (int s = 0; s < 3; s++) {
+    int64_t nn = D.N[s] + D.nbc[1 + s];
+    if (nn > D.cap[s]) {
+      nn = D.cap[s];
+      atomicOr(&D.ctr->err, ERR_CAP);
+    }
+    D.N[s] = nn;
+    D.nbc[1 + s] = 0;
+  }
+  D.ctr->next_id += B;
+  D.ctr->births += B;
+  if ((uint64_t)D.ctr->next_id > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
+  D.nbc[0] = 0;
+  *D.nreq = 0;
+}
+
 // close the rf cycle: move the accumulated sums to the last-cycle buffers
 template <class R>
 __device__ void close_cycle(const Consts<R>& C, const Dev<R>& D) {
@@ -1791,23 +1825,8 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
   __syncthreads();
   births_phase(C, D, U.cur, part, bkeys);
   __syncthreads();
-  int B = D.nbc[0];
-  if (B > D.nb_cap) B = D.nb_cap;
   if (tid == 0) {
-    for (int s = 0; s < 3; s++) {
-      int64_t nn = D.N[s] + D.nbc[1 + s];
-      if (nn > D.cap[s]) {
-        nn = D.cap[s];
-        atomicOr(&D.ctr->err, ERR_CAP);
-      }
-      D.N[s] = nn;
-      D.nbc[1 + s] = 0;
-    }
-    D.ctr->next_id += B;
-    D.ctr->births += B;
-    if ((uint64_t)D.ctr->next_id > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
-    D.nbc[0] = 0;
-    *D.nreq = 0;
+    close_births(D);
     D.ctr->step = n + 1;
   }
   if (split) return;

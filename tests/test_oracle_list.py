@@ -271,7 +271,7 @@ def _list_small(**kw):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_count_balance_every_pass(prec):
-    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST / 20)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     wl = _list_small()
     o = O.Oracle(wl, sig, thr, loss, precision=prec)
     prev_ev, prev_ab, _ = o.counters()
@@ -295,7 +295,7 @@ def test_count_balance_every_pass(prec):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
 def test_per_event_conservation_in_the_list(prec, tol):
-    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST / 20)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
     o = O.Oracle(_list_small(), sig, thr, loss, precision=prec)
     o.log_enable(400_000)
     o.step(200)
