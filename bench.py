@@ -32,7 +32,10 @@ Other modes: ``--workload sweep`` (many discharges advanced together),
 ``--workload serve`` (the serving loop over a request stream),
 ``--workload ablation`` (the metastable pair C = 0 / C = 1/6 on the production
 discharge); ``--coulomb-inter`` adds the unlike-species Coulomb pass to a
-single-discharge run and reports its longest collision chains.
+single-discharge run and reports its longest collision chains; ``--dsmc``
+replaces the null-collision MCC of every push by the paper's per-cell
+collision list every sort_every steps (the push kernel then moves and deposits
+only, and the roofline prices it with the same bytes).
 """
 from __future__ import annotations
 
@@ -51,7 +54,8 @@ BYTES_PER_STEP = {"fp32": 48, "fp64": 80}      # whole particle state read and w
 BYTES_TOUCHED = {"fp32": 32, "fp64": 48}       # cell, off, vx read and written, id read
 TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "traffic_k_push.json"),
                  "fp64": os.path.join(ROOT, "profiles", "traffic_k_push_fp64.json")}
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0705_0495_amd", "csrc", f) for f in ("pic_kernels.hpp", "pic.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0705_0495_amd", "csrc", f)
+                  for f in ("pic_kernels.hpp", "pic_list.hpp", "pic.hip")]
 
 
 def kernel_source_sha():
@@ -94,6 +98,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-derived push grid")
+    ap.add_argument("--dsmc", action="store_true",
+                    help="collisions (4)-(19) as the per-cell list of Sec. II every sort_every steps")
     ap.add_argument("--coulomb-inter", action="store_true",
                     help="large/prod/small: unlike-species Coulomb collisions as well (off in the paper's runs)")
     ap.add_argument("--cpu-steps", type=int, default=800)
@@ -120,6 +126,8 @@ def main():
     wl = workload(args.workload)
     if args.coulomb_inter:
         wl = dataclasses.replace(wl, coulomb_inter=True)
+    if args.dsmc:
+        wl = dataclasses.replace(wl, dsmc=True)
     sig, thr, loss = build_tables()
     t0 = time.time()
     cap = [4 * n + (1 << 20) for n in wl.n_init]
@@ -267,6 +275,8 @@ def main():
                                f"{sum(wl.n_init)} macro particles {tuple(wl.n_init)}",
                    "ion_subcycle": wl.ion_subcycle, "sort_every": wl.sort_every,
                    "coulomb_every": wl.coulomb_every, "coulomb_inter": bool(wl.coulomb_inter),
+                   "collisions": "per-cell list every sort_every steps (Sec. II)" if wl.dsmc
+                   else "null-collision MCC every push",
                    "precision": args.precision, "push_grid": grid,
                    "push_shape": list(d.launch_shape()[:2])},
         "roofline": roofline,

@@ -63,18 +63,16 @@ __device__ __forceinline__ uint32_t list_step(const Dev<R>& D) {
   return (uint32_t)(D.ctr->step - 1);
 }
 
-// One gas type T of species S for one particle: the decision uniform; below
-// the type's largest probability a molecule from the Maxwellian at T_gas,
-// then the channels of the type in order against the same uniform.  Returns
-// false when the particle is consumed; moved is set when it collided.
-template <class R, int S, int T>
-__device__ __forceinline__ bool list_gas(const Consts<R>& C, const Dev<R>& D, const ListK& K, ListLds& G, int cell,
-                                         R off, uint64_t id, R v[3], uint32_t n, bool& moved) {
-  constexpr int J0 = LIST_CH0[T], NC = LIST_NCH[T];
-  const uint4 w = rng(C, id, n, lk_dec(T));
-  const double U = unif52(w.x, w.y);
-  if (!(U < K.B[T])) return true;
-  const uint4 u = rng(C, id, n, lk_gas(T));
+// One gas type t of species S for one particle whose decision uniform U
+// (stream lk_dec(t)) is below the type's largest probability: a molecule from
+// the Maxwellian at T_gas, then the channels of the type in order against U.
+// Returns false when the particle is consumed; moved is set when it collided.
+// (t is a constant wherever this is inlined: the callers' loops unroll.)
+template <class R, int S>
+__device__ __forceinline__ bool list_gas(const Consts<R>& C, const Dev<R>& D, const ListK& K, ListLds& G, int t,
+                                         int cell, R off, uint64_t id, R v[3], uint32_t n, double U, bool& moved) {
+  const int J0 = LIST_CH0[t], NC = LIST_NCH[t];
+  const uint4 u = rng(C, id, n, lk_gas(t));
   const R r1 = bm_radius<R>(C, unif<R>(u.x)), a1 = unif<R>(u.y);
   const R r2 = bm_radius<R>(C, unif<R>(u.z)), a2 = unif<R>(u.w);
   R vt[3];
@@ -100,26 +98,43 @@ __device__ __forceinline__ bool list_gas(const Consts<R>& C, const Dev<R>& D, co
   if (hit < 0) return true;
   atomicAdd(&G.ev[hit], 1);
   moved = true;
-  return gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n, lk_ang(T));
+  return gas_event<R, S>(C, D, hit, cell, off, id, v, vt, g, Erel, n, lk_ang(t));
 }
 
-// the gas types Ts... (in order) for every alive particle of species S
+// The gas types Ts... (in order) for every alive particle of species S.  The
+// decision uniforms of all the types are drawn first (independent streams,
+// so their generators overlap); a particle below none of the bounds is done
+// without reading its velocity.
 template <class R, int S, int... Ts>
 __device__ __forceinline__ void list_species(const Consts<R>& C, const Dev<R>& D, const ListK& K, ListLds& G,
                                              uint32_t n) {
+  constexpr int NT = sizeof...(Ts);
+  constexpr int TT[NT] = {Ts...};
   const Store<R> st = D.st[S];
   const int64_t Ns = D.N[S];
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Ns; i += step) {
     const int cell = st.cell[i];
     if (cell == DEAD) continue;
-    const R off = st.off[i];
     const uint64_t id = st.id[i];
+    double U[NT];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      const uint4 w = rng(C, id, n, lk_dec(TT[q]));
+      U[q] = unif52(w.x, w.y);
+      any = any || U[q] < K.B[TT[q]];
+    }
+    if (!any) continue;
+    const R off = st.off[i];
     R v[3];
     v[0] = st.vx[i];
     ld_yz(st, i, v[1], v[2]);
-    bool moved = false;
-    const bool alive = (list_gas<R, S, Ts>(C, D, K, G, cell, off, id, v, n, moved) && ...);
+    bool moved = false, alive = true;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      if (alive && U[q] < K.B[TT[q]]) alive = list_gas<R, S>(C, D, K, G, TT[q], cell, off, id, v, n, U[q], moved);
+    }
     if (!alive) {
       st.cell[i] = DEAD;
       deposit_global(D, C.N, S, cell, off, -1);
@@ -175,7 +190,10 @@ template <int T> struct ListPair {
 // segment of the last sort, dead ones skipped) and accepts with
 // U < N_t(c) KPl sigma g.  Accepted requests go to the list and reset their
 // partner's claim word (the id array of the partner species' idle sort
-// buffer).
+// buffer).  The waves walk the test particles 64 at a time; a wave scans the
+// segment of each of its requests with all its lanes (a segment holds
+// thousands of partners in a dense discharge) and reduces the keys by
+// shuffles (keys end in the partner id, so they are distinct).
 template <class R, int T>
 __global__ void __launch_bounds__(LIST_TPB) k_list_pick(const Consts<R>* __restrict__ Cp,
                                                         const Dev<R>* __restrict__ Dp, ListK K) {
@@ -187,61 +205,86 @@ __global__ void __launch_bounds__(LIST_TPB) k_list_pick(const Consts<R>* __restr
   __syncthreads();
   const uint32_t n = list_step(D);
   const int N = C.N;
+  const int lane = threadIdx.x & 63;
   const Store<R> st = D.st[PT::S], ps = D.st[PT::P];
   uint64_t* claim = D.alt[PT::P].id;
   const int32_t* cnt = D.cnt + (size_t)PT::P * N;
   const int32_t* seg = D.seg + (size_t)PT::P * (N + 1);
   const int64_t Ns = D.N[PT::S];
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Ns; i += step) {
-    const int cell = st.cell[i];
-    if (cell == DEAD) continue;
-    const double Nt = (double)cnt[cell];
-    if (Nt * K.KM[PT::PI] > 1.0) {
-      atomicOr(&D.ctr->err, ERR_PMAX);
-      continue;
-    }
-    const uint64_t id = st.id[i];
-    const uint4 w = rng(C, id, n, lk_dec(T));
-    const double U = unif52(w.x, w.y);
-    if (!(U < Nt * K.KM[PT::PI])) continue;
-    uint64_t best = ~0ull;
-    int32_t b = -1;
-    for (int32_t k = seg[cell]; k < seg[cell + 1]; k++) {
-      if (ps.cell[k] == DEAD) continue;
-      const uint64_t key = pick_key(C, ps.id[k], id, n);
-      if (key < best) {
-        best = key;
-        b = k;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < Ns; base += nwaves * 64) {
+    const int64_t i = base + lane;
+    int cell = DEAD;
+    uint64_t id = 0;
+    double U = 0.0, Nt = 0.0;
+    bool want = false;
+    if (i < Ns) cell = st.cell[i];
+    if (cell != DEAD) {
+      Nt = (double)cnt[cell];
+      if (Nt * K.KM[PT::PI] > 1.0) {
+        atomicOr(&D.ctr->err, ERR_PMAX);
+      } else {
+        id = st.id[i];
+        const uint4 w = rng(C, id, n, lk_dec(T));
+        U = unif52(w.x, w.y);
+        want = U < Nt * K.KM[PT::PI];
       }
     }
-    atomicAdd(&G.nreq, 1);
-    if (b < 0) continue;
-    R ty, tz, py, pz;
-    ld_yz(st, i, ty, tz);
-    ld_yz(ps, b, py, pz);
-    const R gx = st.vx[i] - ps.vx[b], gy = ty - py, gz = tz - pz;
-    const R g2 = (gx * gx + gy * gy) + gz * gz;
-    const R g = Sqrt(g2);
-    const R Erel = C.hmu_c[PT::PI] * g2;
-    R sg = 0;
-    if (Erel >= C.thr[PT::J]) sg = sig_at(D.sig, TS, PT::J, lookup(Erel)) * g;
-    if (!(U < (Nt * K.KPl) * (double)sg)) continue;
-    const int r = atomicAdd(D.nreq, 1);
-    if (r < D.lreq_cap) {
-      Request<R> q;
-      q.sp = PT::S;
-      q.chan = PT::J;
-      q.slot = (int32_t)i;
-      q.cell = cell;
-      q.id = id;
-      q.u_acc = (R)0;
-      q.partner = b;
-      q.acc = 0;
-      D.lreq[r] = q;
-      claim[b] = ~0ull;
-    } else {
-      atomicOr(&D.ctr->err, ERR_REQ);
+    uint64_t pending = __ballot(want);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int lc = __shfl(cell, leader);
+      const uint64_t lid = __shfl(id, leader);
+      uint64_t best = ~0ull;
+      int32_t b = -1;
+      for (int32_t k = seg[lc] + lane; k < seg[lc + 1]; k += 64) {
+        if (ps.cell[k] == DEAD) continue;
+        const uint64_t key = pick_key(C, ps.id[k], lid, n);
+        if (key < best) {
+          best = key;
+          b = k;
+        }
+      }
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) {
+        const uint64_t ok = __shfl_xor(best, d);
+        const int32_t ob = __shfl_xor(b, d);
+        if (ok < best) {
+          best = ok;
+          b = ob;
+        }
+      }
+      if (lane != leader) continue;
+      atomicAdd(&G.nreq, 1);
+      if (b < 0) continue;
+      R ty, tz, py, pz;
+      ld_yz(st, i, ty, tz);
+      ld_yz(ps, b, py, pz);
+      const R gx = st.vx[i] - ps.vx[b], gy = ty - py, gz = tz - pz;
+      const R g2 = (gx * gx + gy * gy) + gz * gz;
+      const R g = Sqrt(g2);
+      const R Erel = C.hmu_c[PT::PI] * g2;
+      R sg = 0;
+      if (Erel >= C.thr[PT::J]) sg = sig_at(D.sig, TS, PT::J, lookup(Erel)) * g;
+      if (!(U < (Nt * K.KPl) * (double)sg)) continue;
+      const int r = atomicAdd(D.nreq, 1);
+      if (r < D.lreq_cap) {
+        Request<R> q;
+        q.sp = PT::S;
+        q.chan = PT::J;
+        q.slot = (int32_t)i;
+        q.cell = cell;
+        q.id = id;
+        q.u_acc = (R)0;
+        q.partner = b;
+        q.acc = 0;
+        D.lreq[r] = q;
+        claim[b] = ~0ull;
+      } else {
+        atomicOr(&D.ctr->err, ERR_REQ);
+      }
     }
   }
   __syncthreads();

@@ -79,6 +79,30 @@ def test_list_larger_discharge_matches_oracle(prec):
         compare(g, o, prec, f"list x8 step {target}")
 
 
+def test_list_large_size_matches_oracle():
+    """The 2^25-particle discharge of the benchmark on the list (bench.py
+    --dsmc): 20 steps, two passes each followed by Coulomb; step 1 on every
+    997th particle, steps 10 (the first pass) and 20 on every particle,
+    counters and charge in full."""
+    wl = dataclasses.replace(workload("large"), dsmc=True)
+    sig, thr, loss = build_tables()
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    g.step(1)
+    o.step(1)
+    compare(g, o, "fp32", "large list step 1", sample_mod=997)
+    done = 1
+    for target in (10, 20):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        compare(g, o, "fp32", f"large list step {target}")
+    ev = o.counters()[0]
+    assert ev[0] > 0 and ev[11] > 0
+    g.close()
+    o.close()
+
+
 def test_list_graph_replay_matches_eager():
     """Whole periods (two passes with their re-sorts) captured and replayed,
     eager steps in between: the eager run's state after every chunk."""
