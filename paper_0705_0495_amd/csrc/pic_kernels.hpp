@@ -1526,21 +1526,33 @@ struct ClaimLds {
 template <class R>
 __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, int nr, uint32_t n) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int NWV = TAIL_TPB / 64;
   const int N = C.N;
-  // one wave per request: scan the partner segment, minimum key by shuffles
-  // (keys end in the partner id, so they are distinct)
-  for (int r = tid >> 6; r < nr; r += TAIL_TPB / 64) {
+  __shared__ uint64_t kmin[NWV];
+  // the smallest key over lanes sub*64 + lane, stepping per*64, of request
+  // r's partner segment (keys end in the partner id, so they are distinct);
+  // four loads in flight per lane
+  auto scan = [&](int r, int sub, int per, uint64_t& best, int32_t& bslot) {
     const Request<R> q = D.req[r];
     const int t = (q.chan == 13) ? 1 : 2;
     const int32_t lo = D.seg[t * (N + 1) + q.cell], hi = D.seg[t * (N + 1) + q.cell + 1];
-    uint64_t best = ~0ull;
-    int32_t bslot = -1;
-    for (int32_t i = lo + lane; i < hi; i += 64) {
-      const uint64_t k = pick_key(C, D.st[t].id[i], q.id, n);
-      if (k < best) {
-        best = k;
-        bslot = i;
+    const uint64_t* ids = D.st[t].id;
+    const int stride = per * 64;
+    best = ~0ull;
+    bslot = -1;
+    for (int32_t i = lo + sub * 64 + lane; i < hi; i += 4 * stride) {
+      uint64_t id4[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) id4[u] = (i + u * stride < hi) ? ids[i + u * stride] : 0;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (i + u * stride >= hi) continue;
+        const uint64_t k = pick_key(C, id4[u], q.id, n);
+        if (k < best) {
+          best = k;
+          bslot = i + u * stride;
+        }
       }
     }
 #pragma unroll
@@ -1552,27 +1564,59 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
         bslot = os;
       }
     }
-    if (lane == 0) {
-      const int32_t p = bslot;
-      int acc = 0;
-      if (p >= 0 && D.st[t].cell[p] != DEAD) {
-        const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
-        const Store<R> ts = D.st[q.sp], ps = D.st[t];
-        R ty, tz, py, pz;
-        ld_yz(ts, q.slot, ty, tz);
-        ld_yz(ps, p, py, pz);
-        const R gx = ts.vx[q.slot] - ps.vx[p], gy = ty - py, gz = tz - pz;
-        const R g2 = (gx * gx + gy * gy) + gz * gz;
-        const R g = Sqrt(g2);
-        const R Erel = C.hmu_c[pi] * g2;
-        R sg = 0;
-        if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, TS, q.chan, lookup(Erel)) * g;
-        acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
+  };
+  // acceptance of request r with partner p (-1: none), one lane
+  auto accept = [&](int r, int32_t p) {
+    const Request<R> q = D.req[r];
+    const int t = (q.chan == 13) ? 1 : 2;
+    int acc = 0;
+    if (p >= 0 && D.st[t].cell[p] != DEAD) {
+      const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
+      const Store<R> ts = D.st[q.sp], ps = D.st[t];
+      R ty, tz, py, pz;
+      ld_yz(ts, q.slot, ty, tz);
+      ld_yz(ps, p, py, pz);
+      const R gx = ts.vx[q.slot] - ps.vx[p], gy = ty - py, gz = tz - pz;
+      const R g2 = (gx * gx + gy * gy) + gz * gz;
+      const R g = Sqrt(g2);
+      const R Erel = C.hmu_c[pi] * g2;
+      R sg = 0;
+      if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, TS, q.chan, lookup(Erel)) * g;
+      acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
+    }
+    L.rpart[r] = p;
+    L.rid[r] = q.id;
+    L.racc[r] = (uint8_t)acc;
+    L.rwin[r] = 0;
+  };
+  if (nr >= NWV) {
+    // one wave per request
+    for (int r = wv; r < nr; r += NWV) {
+      uint64_t best;
+      int32_t bslot;
+      scan(r, 0, 1, best, bslot);
+      if (lane == 0) accept(r, bslot);
+    }
+  } else {
+    // fewer requests than waves: NWV / nr waves share each segment (a dense
+    // discharge has thousands of partners per cell), minimum through LDS
+    const int per = NWV / nr;
+    const int r = wv / per, sub = wv % per;
+    if (tid < nr) kmin[tid] = ~0ull;
+    __syncthreads();
+    uint64_t best = ~0ull;
+    int32_t bslot = -1;
+    if (r < nr) {
+      scan(r, sub, per, best, bslot);
+      if (lane == 0 && bslot >= 0) atomicMin((unsigned long long*)&kmin[r], (unsigned long long)best);
+    }
+    __syncthreads();
+    if (r < nr && lane == 0) {
+      if (kmin[r] == ~0ull) {
+        if (sub == 0) accept(r, -1);
+      } else if (bslot >= 0 && best == kmin[r]) {
+        accept(r, bslot);
       }
-      L.rpart[r] = p;
-      L.rid[r] = q.id;
-      L.racc[r] = (uint8_t)acc;
-      L.rwin[r] = 0;
     }
   }
   __syncthreads();
