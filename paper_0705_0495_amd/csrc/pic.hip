@@ -656,9 +656,9 @@ struct Impl : Base {
   const Dev<R>* dpar() const { return dD + (D.st[0].cell == dev_parity0_cell ? 0 : 1); }
 
   // the per-cell collision list after the sort of this step's end: the types
-  // in the order of Table I, births placed after each type that makes them,
-  // the sort repeated before impact detachment (19) (its O- partners include
-  // those born in (15)) and at the end
+  // in the order of Table I, births placed after each type that makes them
+  // (at the end of their stores, where the partner choice of impact
+  // detachment (19) finds the O- born in (15)), the sort repeated at the end
   void list_partner_kernels(int t, int grid) {
     const Dev<R>* dp = dpar();
     const int gc = 64;
@@ -692,9 +692,6 @@ struct Impl : Base {
     hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
     hipLaunchKernelGGL((k_list_gas<R, 14>), dim3(grid), dim3(LIST_TPB), 0, c->stream, dC, dp, LK);
     hipLaunchKernelGGL(k_list_commit<R>, dim3(1), dim3(TAIL_TPB), 0, c->stream, dC, dp);
-    HIPCHK(c, hipGetLastError());
-    int rc = sort();
-    if (rc) return rc;
     list_partner_kernels(15, grid);
     HIPCHK(c, hipGetLastError());
     return sort();

@@ -1976,6 +1976,13 @@ constexpr int SORT_CHUNK = SORT_TPB * SORT_PER;
 constexpr int SORT_WIN = 512;  // cells around the middle of a chunk
 
 template <class R>
+struct SortRegs {
+  int32_t cell[SORT_PER];
+  R off[SORT_PER], vx[SORT_PER], vy[SORT_PER], vz[SORT_PER];
+  uint64_t id[SORT_PER];
+};
+
+template <class R>
 struct SortLds {
   int32_t cnt[SORT_WIN];   // particles of the chunk per window cell
   int32_t lst[SORT_WIN];   // their first position in the staged chunk
@@ -2008,8 +2015,9 @@ __device__ __forceinline__ void k_sort_scatter_body(const Consts<R>& C, const De
     nch[s] = (Ns[s] + SORT_CHUNK - 1) / SORT_CHUNK;
   }
   const int64_t total = nch[0] + nch[1] + nch[2];
-  for (int64_t t = B.x; t < total; t += B.n) {
-    int s = 0;
+  // chunk t: species and first slot
+  auto chunk = [&](int64_t t, int& s, int64_t& c0) {
+    s = 0;
     int64_t c = t;
     if (c >= nch[0]) {
       c -= nch[0];
@@ -2019,32 +2027,56 @@ __device__ __forceinline__ void k_sort_scatter_body(const Consts<R>& C, const De
         s = 2;
       }
     }
-    const int64_t c0 = c * SORT_CHUNK;
-    const Store<R> a = D.st[s], b = D.alt[s];
-    int32_t* cur = D.cursor + (size_t)s * N;
-    const int32_t* seg = D.seg + (size_t)s * (N + 1);
-    if (tid == 0) {
-      int32_t cm = a.cell[min(c0 + SORT_CHUNK / 2, Ns[s] - 1)];
-      if (cm == DEAD) cm = a.cell[c0];
-      if (cm == DEAD) cm = 0;
-      L.wbase = cm - SORT_WIN / 2;
-    }
-    for (int i = tid; i < SORT_WIN; i += SORT_TPB) L.cnt[i] = 0;
-    int32_t cell[SORT_PER], rank[SORT_PER];
-    R off[SORT_PER], vx[SORT_PER], vy[SORT_PER], vz[SORT_PER];
-    uint64_t id[SORT_PER];
+    c0 = c * SORT_CHUNK;
+  };
+  // the thread's particles of chunk t (dead past the store's end)
+  auto load = [&](int64_t t, SortRegs<R>& q) {
+    int s;
+    int64_t c0;
+    chunk(t, s, c0);
+    const Store<R> a = D.st[s];
 #pragma unroll
     for (int j = 0; j < SORT_PER; j++) {
       const int64_t slot = c0 + (int64_t)j * SORT_TPB + tid;
       const bool in = slot < Ns[s];
-      cell[j] = in ? a.cell[slot] : DEAD;
-      off[j] = in ? a.off[slot] : (R)0;
-      vx[j] = in ? a.vx[slot] : (R)0;
-      vy[j] = (R)0;
-      vz[j] = (R)0;
-      if (in) ld_yz(a, slot, vy[j], vz[j]);
-      id[j] = in ? a.id[slot] : 0;
+      q.cell[j] = in ? a.cell[slot] : DEAD;
+      q.off[j] = in ? a.off[slot] : (R)0;
+      q.vx[j] = in ? a.vx[slot] : (R)0;
+      q.vy[j] = (R)0;
+      q.vz[j] = (R)0;
+      if (in) ld_yz(a, slot, q.vy[j], q.vz[j]);
+      q.id[j] = in ? a.id[slot] : 0;
     }
+  };
+  // the next chunk's particles are loaded while this one is ranked, staged
+  // and written
+  SortRegs<R> P;
+  if (B.x < total) load(B.x, P);
+  for (int64_t t = B.x; t < total; t += B.n) {
+    int s;
+    int64_t c0;
+    chunk(t, s, c0);
+    const Store<R> b = D.alt[s];
+    int32_t* cur = D.cursor + (size_t)s * N;
+    const int32_t* seg = D.seg + (size_t)s * (N + 1);
+    if (tid == 0) {
+      // the window is centred on the chunk's middle particle (thread 0 holds
+      // slot c0 + SORT_CHUNK / 2); where it sits changes only which cells
+      // take the global path
+      const int32_t cm = P.cell[SORT_PER / 2] != DEAD ? P.cell[SORT_PER / 2] : (P.cell[0] != DEAD ? P.cell[0] : 0);
+      L.wbase = cm - SORT_WIN / 2;
+    }
+    for (int i = tid; i < SORT_WIN; i += SORT_TPB) L.cnt[i] = 0;
+    int32_t rank[SORT_PER];
+    int32_t* cell = P.cell;
+    R* off = P.off;
+    R* vx = P.vx;
+    R* vy = P.vy;
+    R* vz = P.vz;
+    uint64_t* id = P.id;
+    SortRegs<R> Q;
+    const bool more = t + B.n < total;
+    if (more) load(t + B.n, Q);
     __syncthreads();
     const int base = L.wbase;
 #pragma unroll
@@ -2142,6 +2174,7 @@ __device__ __forceinline__ void k_sort_scatter_body(const Consts<R>& C, const De
       b.id[dst] = L.id[k];
     }
     __syncthreads();
+    if (more) P = Q;
   }
   if (!last_block(&D.done[2], B.n)) return;
   if (threadIdx.x == 0) {

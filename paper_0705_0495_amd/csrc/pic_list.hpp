@@ -9,7 +9,10 @@
 // One kernel per group of types that leaves the populations alone (gas types
 // of one or all species), and for each partner type three: decisions and
 // partner choice, claims (smallest test id per partner), collisions.  Births
-// are placed by a one-workgroup kernel after each type that can make them.
+// are placed by a one-workgroup kernel after each type that can make them;
+// they join the end of their store, where the partner choice of a later type
+// finds them (the O- of (15) for (19)); the sort after the pass puts them
+// into their cells.
 #pragma once
 #include "pic_kernels.hpp"
 
@@ -187,7 +190,8 @@ template <int T> struct ListPair {
 // Partner type T, decisions: each alive test particle draws its uniform;
 // below N_t(c) KPl M_j (N_t(c) the partners alive in its cell now) it takes
 // the partner of its cell with the smallest hash of the two ids (the cell's
-// segment of the last sort, dead ones skipped) and accepts with
+// segment of the last sort and the partners born since, dead ones skipped)
+// and accepts with
 // U < N_t(c) KPl sigma g.  Accepted requests go to the list and reset their
 // partner's claim word (the id array of the partner species' idle sort
 // buffer).  The waves walk the test particles 64 at a time; a wave scans the
@@ -211,6 +215,7 @@ __global__ void __launch_bounds__(LIST_TPB) k_list_pick(const Consts<R>* __restr
   const int32_t* cnt = D.cnt + (size_t)PT::P * N;
   const int32_t* seg = D.seg + (size_t)PT::P * (N + 1);
   const int64_t Ns = D.N[PT::S];
+  const int64_t tail0 = seg[N], Np = D.N[PT::P];  // partners placed since the sort: [tail0, Np)
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t base = wave * 64; base < Ns; base += nwaves * 64) {
@@ -245,6 +250,16 @@ __global__ void __launch_bounds__(LIST_TPB) k_list_pick(const Consts<R>* __restr
         if (key < best) {
           best = key;
           b = k;
+        }
+      }
+      // partners born since the sort (the O- of (15) for (19)) follow the
+      // sorted stores, in any cell
+      for (int64_t k = tail0 + lane; k < Np; k += 64) {
+        if (ps.cell[k] != lc) continue;
+        const uint64_t key = pick_key(C, ps.id[k], lid, n);
+        if (key < best) {
+          best = key;
+          b = (int32_t)k;
         }
       }
 #pragma unroll
