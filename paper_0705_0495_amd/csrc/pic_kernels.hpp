@@ -2514,8 +2514,8 @@ constexpr int COUL_TINY = 512;   // one wave: many workgroups per CU for the man
 constexpr int COUL_TTPB = 64;
 constexpr int COUL_SMALL = 2048;
 constexpr int COUL_STPB = 256;
-constexpr int COUL_MID = 5120;   // two workgroups per CU in FP32
-constexpr int COUL_MTPB = 512;
+constexpr int COUL_MID = 5120;   // two workgroups per CU in FP32 (one per LDS half)
+constexpr int COUL_MTPB = 1024;  // with at most 64 VGPRs: eight waves per SIMD
 
 template <class R, int M, int TPB>
 struct CoulLds {
@@ -2685,8 +2685,9 @@ __global__ void __launch_bounds__(TPB) k_coul_large_b(const Consts<R>* __restric
   }
 }
 
+// (the 1024-thread class asks for eight waves per SIMD, two workgroups per CU)
 template <class R, int M, int TPB, int MLO, bool LIST>
-__global__ void __launch_bounds__(TPB) k_coulomb(Consts<R> C, Dev<R> D) {
+__global__ void __launch_bounds__(TPB, TPB == 1024 ? 8 : 1) k_coulomb(Consts<R> C, Dev<R> D) {
   k_coulomb_body<R, M, TPB, MLO, LIST>(C, D, Blk{(int)blockIdx.x, (int)gridDim.x});
 }
 
