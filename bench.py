@@ -59,11 +59,16 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_0705_0495_amd", "csrc", f)
 
 
 def kernel_source_sha():
-    """Hash of the HIP sources: counter files name the sources they were taken from."""
+    """Hash of the HIP sources' code (comments and blank lines left out):
+    counter files name the code they were taken from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        text = open(f, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -191,10 +191,9 @@ template <int T> struct ListPair {
 // below N_t(c) KPl M_j (N_t(c) the partners alive in its cell now) it takes
 // the partner of its cell with the smallest hash of the two ids (the cell's
 // segment of the last sort and the partners born since, dead ones skipped)
-// and accepts with
-// U < N_t(c) KPl sigma g.  Accepted requests go to the list and reset their
-// partner's claim word (the id array of the partner species' idle sort
-// buffer).  The waves walk the test particles 64 at a time; a wave scans the
+// and accepts with U < N_t(c) KPl sigma g.  Accepted requests go to the list
+// and reset their partner's claim word (the id array of the partner
+// species' idle sort buffer).  The waves walk the test particles 64 at a time; a wave scans the
 // segment of each of its requests with all its lanes (a segment holds
 // thousands of partners in a dense discharge) and reduces the keys by
 // shuffles (keys end in the partner id, so they are distinct).
