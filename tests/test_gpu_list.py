@@ -140,6 +140,39 @@ def test_list_discharge_in_a_batch_steps_alone():
         _same_state(_state(alone), _state(g), f"{'list' if w.dsmc else 'null'} in a batch")
 
 
+def test_list_with_unlike_coulomb_matches_oracle():
+    """The list followed by both Coulomb passes (like and unlike species)
+    after its sort."""
+    wl = list_small(coulomb_inter=True)
+    sig, thr, loss = build_tables(partner_boost=LIST_BOOST)
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    done = 0
+    for target in (10, 30, 60):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        g.sync()
+        compare(g, o, "fp32", f"list + unlike Coulomb step {done}")
+
+
+def test_allocation_free_batch_refuses_list_discharges():
+    """pic_step_batch_static batches only what pic_step_batch would: a
+    discharge on the list is refused (an argument error that leaves it
+    usable)."""
+    from paper_0705_0495_amd import PicError, step_batch_static
+    sig, thr, loss = build_tables()
+    a = _gpu()(list_small(), sig, thr, loss, precision="fp32")
+    b = _gpu()(ragged_small(dsmc=True, seed=705049778), sig, thr, loss, precision="fp32")
+    with pytest.raises(PicError):
+        step_batch_static([a, b], 20)
+    a.step(20)
+    a.sync()
+    o = O.Oracle(list_small(), sig, thr, loss, precision="fp32")
+    o.step(20)
+    compare(a, o, "fp32", "list after a refused static batch")
+
+
 def test_list_bounds_are_rejected_or_raised():
     from paper_0705_0495_amd import PicError
     sig, thr, loss = build_tables()
