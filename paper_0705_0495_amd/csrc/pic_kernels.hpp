@@ -1412,9 +1412,11 @@ __device__ __forceinline__ void k_push_body(const Consts<R>& C, const Dev<R>& D,
                         ab[1][1]);
   push_loop<R, 2, ELDS, SH>(C, D, L.u.p.win, L.G, El, u0[2], nt[2], B, buf, Ns[2], n, T0[2], pm[2], ps, ab[2][0],
                         ab[2][1]);
-  collide_species<R, 0, ELDS, SH>(C, D, L, u0[0], nt[0], B, n);
-  collide_species<R, 1, ELDS, SH>(C, D, L, u0[1], nt[1], B, n);
-  collide_species<R, 2, ELDS, SH>(C, D, L, u0[2], nt[2], B, n);
+  // (no collision phase where the null-collision bound is zero: the per-cell
+  // collision list replaces it)
+  if (T0[0] != 0) collide_species<R, 0, ELDS, SH>(C, D, L, u0[0], nt[0], B, n);
+  if (T0[1] != 0) collide_species<R, 1, ELDS, SH>(C, D, L, u0[1], nt[1], B, n);
+  if (T0[2] != 0) collide_species<R, 2, ELDS, SH>(C, D, L, u0[2], nt[2], B, n);
   // [electrode][species]
   for (int s = 0; s < 3; s++) {
     if (ab[s][0]) atomicAdd(&L.G.absorbed[s], ab[s][0]);
