@@ -38,6 +38,8 @@ def compare(g, o, prec, label, sample_mod=None):
         gi, gc, go, gv = _by_id(g.particles(s))
         oi, oc, oo, ov = _by_id(o.particles(s))
         assert len(gi) == len(oi), f"{label} species {s}: {len(gi)} vs {len(oi)} particles"
+        if len(gi) == 0:
+            continue
         if sample_mod:
             kg, ko = gi % sample_mod == 0, oi % sample_mod == 0
             gi, gc, go, gv = gi[kg], gc[kg], go[kg], gv[kg]
