@@ -88,6 +88,11 @@ WORKLOADS = {
     "large": Workload("large", 0.06, 4096, 100.0, 400.0, 13.56e6, 8000, 1,
                       (13_421_773, 3_355_443, 16_777_216), sort_every=10, coulomb_every=10,
                       seed=705049503),
+    # the small discharge with the collisions (4)-(19) as the per-cell list
+    # every 10 steps
+    "small_list": Workload("small_list", 0.04, 128, 10.0, 100.0, 13.56e6, 1000, 1,
+                           (10_000, 2_000, 10_000), sort_every=10, coulomb_every=10, seed=705049501,
+                           dsmc=True),
 }
 
 

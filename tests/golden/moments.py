@@ -8,6 +8,7 @@ oracle is called; the result is written to
 ``<workload>_<precision>_moments.npz`` next to this file.
 
     python tests/golden/moments.py small            # 20 cycles, average 11-20
+    python tests/golden/moments.py small_list       # the same on the per-cell collision list
     python tests/golden/moments.py prod --cycles 3 --skip 1
 """
 from __future__ import annotations
@@ -78,7 +79,7 @@ def oracle_run(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["small", "prod"])
+    ap.add_argument("workload", choices=["small", "small_list", "prod"])
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--cycles", type=int, default=20)
     ap.add_argument("--skip", type=int, default=10)

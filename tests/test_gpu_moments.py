@@ -91,6 +91,13 @@ def test_small_long_run_moments_agree_with_fp64_oracle():
         assert err <= max(0.02, 3.0 * expect), (label, err, expect)
 
 
+def test_small_list_long_run_moments_agree_with_fp64_oracle():
+    """The same discharge with the collisions as the per-cell list of Sec. II
+    (every 10 steps): the same bar."""
+    for label, err, mx, spread, expect in statement("small_list"):
+        assert err <= max(0.02, 3.0 * expect), (label, err, expect)
+
+
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "prod_fp64_moments.npz")),
                     reason="oracle moments of the production discharge not generated")
 def test_prod_long_run_moments_agree_with_fp64_oracle_within_2pct():
