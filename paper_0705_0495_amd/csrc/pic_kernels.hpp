@@ -506,6 +506,7 @@ struct FieldLds {
   } v;
   __int128 wsA[FIELD_TPB / 64];
   __int128 wsB[FIELD_TPB / 64];
+  int64_t fb[3][FIELD_PER_MAX][FIELD_TPB / 64];  // F of each wave's last node
   int64_t q0, qN;
 };
 
@@ -530,12 +531,15 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int N = C.N;
-  const double U = D.U[n % C.M];
   const bool ion = (n % C.nsub) == 0;
-  // 1. node charge Q_s[i] = 2^24 cnt[i] - F[i] + F[i-1] (coalesced)
+  // 1. node charge Q_s[i] = 2^24 cnt[i] - F[i] + F[i-1], node i = tid + k *
+  // FIELD_TPB (coalesced); F[i-1] is the left neighbour's F[i], by a shuffle
+  // inside the wave and through LDS across waves.  With the step's
+  // diagnostics (mode 1) the rf-cycle sums take one integer addition per node
+  // and step, by the thread that owns the node: this workgroup is the only
+  // writer, so a plain read-modify-write, its loads in flight with the others
   int32_t cn[3][PER];
-  int64_t Fc[3][PER], Fm[3][PER];
-  double pa[PER];
+  int64_t Fc[3][PER], qa[3][PER];
 #pragma unroll
   for (int s = 0; s < 3; s++)
 #pragma unroll
@@ -543,26 +547,38 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
       const int i = tid + k * FIELD_TPB;
       cn[s][k] = i < N ? D.cnt[s * N + i] : 0;
       Fc[s][k] = i < N ? D.F[s * N + i] : 0;
-      Fm[s][k] = (i >= 1 && i <= N) ? D.F[s * N + i - 1] : 0;
     }
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int i = tid + k * FIELD_TPB;
-    pa[k] = (i <= N && mode == 1) ? D.phiacc[i] : 0.0;
+  for (int s = 0; s < 3; s++)
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = tid + k * FIELD_TPB;
+      qa[s][k] = (i <= N && mode == 1) ? D.Qacc[s * (N + 1) + i] : 0;
+    }
+  if (lane == 63) {
+#pragma unroll
+    for (int s = 0; s < 3; s++)
+#pragma unroll
+      for (int k = 0; k < PER; k++) FL.fb[s][k][wv] = Fc[s][k];
   }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int i = tid + k * FIELD_TPB;
-    if (i > N) continue;
     int64_t Qs[3];
 #pragma unroll
     for (int s = 0; s < 3; s++) {
-      const int64_t v = (((int64_t)cn[s][k] << 24) - Fc[s][k]) + Fm[s][k];
+      int64_t left = __shfl_up(Fc[s][k], 1);
+      if (lane == 0) left = wv > 0 ? FL.fb[s][k][wv - 1] : (k > 0 ? FL.fb[s][k - 1][FIELD_TPB / 64 - 1] : 0);
+      const int64_t Fm = (i >= 1 && i <= N) ? left : 0;
+      const int64_t v = (((int64_t)cn[s][k] << 24) - Fc[s][k]) + Fm;
       Qs[s] = v;
-      D.Qcur[s * (N + 1) + i] = v;
-      // one addition per node and step: the order of the sums is fixed
-      if (mode == 1) atomicAdd((unsigned long long*)&D.Qacc[s * (N + 1) + i], (unsigned long long)v);
+      if (i <= N) {
+        D.Qcur[s * (N + 1) + i] = v;
+        if (mode == 1) D.Qacc[s * (N + 1) + i] = qa[s][k] + v;
+      }
     }
+    if (i > N) continue;
     const int64_t q = (Qs[2] - Qs[0]) - Qs[1];
     FL.v.q[i] = q;
     if (i == 0) FL.q0 = q;
@@ -585,6 +601,7 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
   }
   __syncthreads();
   // 2. potential from the exact discrete Green's function, contiguous nodes
+  const double U = D.U[n % C.M];  // the driven electrode's potential
   const int i0 = min(tid * PER, N + 1);
   const int i1 = min(i0 + PER, N + 1);
   int64_t qloc[PER];
@@ -637,6 +654,13 @@ __device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64
       ph = (x + y) / (double)N;
     }
     FL.v.phi[i] = ph;
+  }
+  // the potential's cycle sums (in flight while the workgroup meets)
+  double pa[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = tid + k * FIELD_TPB;
+    pa[k] = (i <= N && mode == 1) ? D.phiacc[i] : 0.0;
   }
   __syncthreads();
   // 3. field, with the half-cell Gauss law at the electrodes (coalesced)
@@ -1518,12 +1542,15 @@ __device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int
   add_birth(C, D, 0, id, 0, pc, po, vn[0], vn[1], vn[2]);
 }
 
+constexpr int REQ_LDS = 64;  // requests kept in LDS while they are resolved (the rest read from global memory)
 struct ClaimLds {
   int32_t rpart[REQ_CAP];
   uint64_t rid[REQ_CAP];
   uint8_t racc[REQ_CAP];
   uint8_t rwin[REQ_CAP];
+  alignas(16) unsigned char rq[REQ_LDS * sizeof(Request<double>)];
 };
+static_assert(sizeof(Request<float>) <= sizeof(Request<double>), "request slots");
 
 template <class R>
 __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, int nr, uint32_t n) {
@@ -1532,11 +1559,16 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   constexpr int NWV = TAIL_TPB / 64;
   const int N = C.N;
   __shared__ uint64_t kmin[NWV];
+  // the first REQ_LDS requests are read once (one round trip), then from LDS
+  Request<R>* rq = reinterpret_cast<Request<R>*>(L.rq);
+  if (tid < min(nr, REQ_LDS)) rq[tid] = D.req[tid];
+  __syncthreads();
+  auto req = [&](int r) -> Request<R> { return r < REQ_LDS ? rq[r] : D.req[r]; };
   // the smallest key over lanes sub*64 + lane, stepping per*64, of request
   // r's partner segment (keys end in the partner id, so they are distinct);
   // four loads in flight per lane
   auto scan = [&](int r, int sub, int per, uint64_t& best, int32_t& bslot) {
-    const Request<R> q = D.req[r];
+    const Request<R> q = req(r);
     const int t = (q.chan == 13) ? 1 : 2;
     const int32_t lo = D.seg[t * (N + 1) + q.cell], hi = D.seg[t * (N + 1) + q.cell + 1];
     const uint64_t* ids = D.st[t].id;
@@ -1569,22 +1601,28 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   };
   // acceptance of request r with partner p (-1: none), one lane
   auto accept = [&](int r, int32_t p) {
-    const Request<R> q = D.req[r];
+    const Request<R> q = req(r);
     const int t = (q.chan == 13) ? 1 : 2;
     int acc = 0;
-    if (p >= 0 && D.st[t].cell[p] != DEAD) {
-      const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
+    if (p >= 0) {
+      // the partner's cell and both velocities in flight together (the slot
+      // lies in the partner segment: in bounds whether alive or not)
       const Store<R> ts = D.st[q.sp], ps = D.st[t];
+      const int32_t pcell = ps.cell[p];
       R ty, tz, py, pz;
       ld_yz(ts, q.slot, ty, tz);
       ld_yz(ps, p, py, pz);
-      const R gx = ts.vx[q.slot] - ps.vx[p], gy = ty - py, gz = tz - pz;
-      const R g2 = (gx * gx + gy * gy) + gz * gz;
-      const R g = Sqrt(g2);
-      const R Erel = C.hmu_c[pi] * g2;
-      R sg = 0;
-      if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, TS, q.chan, lookup(Erel)) * g;
-      acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
+      const R tvx = ts.vx[q.slot], pvx = ps.vx[p];
+      if (pcell != DEAD) {
+        const int pi = (q.chan == 12) ? 0 : (q.chan == 13 ? 1 : 2);
+        const R gx = tvx - pvx, gy = ty - py, gz = tz - pz;
+        const R g2 = (gx * gx + gy * gy) + gz * gz;
+        const R g = Sqrt(g2);
+        const R Erel = C.hmu_c[pi] * g2;
+        R sg = 0;
+        if (Erel >= C.thr[q.chan]) sg = sig_at(D.sig, TS, q.chan, lookup(Erel)) * g;
+        acc = (q.u_acc * C.Mr_c[pi] < sg) ? 1 : 0;
+      }
     }
     L.rpart[r] = p;
     L.rid[r] = q.id;
@@ -1624,11 +1662,12 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   __syncthreads();
   // stage 1: electron test particles; (13) takes an O2+, (19) an O-
   for (int r = tid; r < nr; r += TAIL_TPB) {
-    const int chan = D.req[r].chan;
-    if (D.req[r].sp != 0 || !L.racc[r]) continue;
+    const Request<R> q = req(r);
+    const int chan = q.chan;
+    if (q.sp != 0 || !L.racc[r]) continue;
     int win = 1;
     for (int r2 = 0; r2 < nr && win; r2++) {
-      if (r2 == r || !L.racc[r2] || D.req[r2].chan != chan) continue;
+      if (r2 == r || !L.racc[r2] || req(r2).chan != chan) continue;
       if (L.rpart[r2] == L.rpart[r] && L.rid[r2] < L.rid[r]) win = 0;
     }
     L.rwin[r] = (uint8_t)win;
@@ -1637,7 +1676,7 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   int nacc = 0;
   for (int r = tid; r < nr; r += TAIL_TPB) {
     if (!L.rwin[r]) continue;
-    const Request<R> q = D.req[r];
+    const Request<R> q = req(r);
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[q.chan], 1ull);
     if (q.chan == 12) {
@@ -1651,12 +1690,13 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   // stage 2: O- test particles (14); the O- must not have been taken by a
   // (19) winner and the O2+ not by a (13) winner
   for (int r = tid; r < nr; r += TAIL_TPB) {
-    if (D.req[r].sp != 1 || !L.racc[r]) continue;
-    const int slot = D.req[r].slot;
+    const Request<R> q = req(r);
+    if (q.sp != 1 || !L.racc[r]) continue;
+    const int slot = q.slot;
     int ok = 1;
     for (int r2 = 0; r2 < nr && ok; r2++) {
       if (L.rwin[r2] != 1) continue;
-      const int c2 = D.req[r2].chan;
+      const int c2 = req(r2).chan;
       if (c2 == 13 && L.rpart[r2] == slot) ok = 0;
       if (c2 == 12 && L.rpart[r2] == L.rpart[r]) ok = 0;
     }
@@ -1675,7 +1715,7 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
   __syncthreads();
   for (int r = tid; r < nr; r += TAIL_TPB) {
     if (L.rwin[r] != 3) continue;
-    const Request<R> q = D.req[r];
+    const Request<R> q = req(r);
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[17], 1ull);
     kill_particle(C, D, 1, q.slot);
@@ -1727,11 +1767,18 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
   if (B > D.nb_cap) B = D.nb_cap;
   if (B == 0) return;
   constexpr int PER = NBUCKET / TAIL_TPB;
-  // bucket counts to LDS (coalesced), exclusive scan over consecutive
-  // buckets per thread, offsets back to global memory (coalesced)
-  for (int i = tid; i < NBUCKET; i += TAIL_TPB) {
-    cur[i] = D.bhist[i];
-    D.bhist[i] = 0;
+  static_assert(NBUCKET % TAIL_TPB == 0, "whole buckets per thread");
+  // bucket counts to LDS (coalesced, every load in flight before the first
+  // store), exclusive scan over consecutive buckets per thread
+  {
+    int32_t h[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) h[q] = D.bhist[tid + q * TAIL_TPB];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      cur[tid + q * TAIL_TPB] = h[q];
+      D.bhist[tid + q * TAIL_TPB] = 0;
+    }
   }
   __syncthreads();
   int loc[PER];
@@ -1796,10 +1843,20 @@ __device__ void births_phase(const Consts<R>& C, const Dev<R>& D, int32_t* cur, 
 // id counter; the birth and request lists are emptied
 template <class R>
 __device__ void close_births(const Dev<R>& D) {
+  // every load before the first store (one round trip)
   int B = D.nbc[0];
-  if (B > D.nb_cap) B = D.nb_cap;
+  int64_t len[3];
+  int32_t add[3];
+#pragma unroll
   for (int s = 0; s < 3; s++) {
-    int64_t nn = D.N[s] + D.nbc[1 + s];
+    len[s] = D.N[s];
+    add[s] = D.nbc[1 + s];
+  }
+  const int64_t next = D.ctr->next_id, births = D.ctr->births;
+  if (B > D.nb_cap) B = D.nb_cap;
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    int64_t nn = len[s] + add[s];
     if (nn > D.cap[s]) {
       nn = D.cap[s];
       atomicOr(&D.ctr->err, ERR_CAP);
@@ -1807,9 +1864,9 @@ __device__ void close_births(const Dev<R>& D) {
     D.N[s] = nn;
     D.nbc[1 + s] = 0;
   }
-  D.ctr->next_id += B;
-  D.ctr->births += B;
-  if ((uint64_t)D.ctr->next_id > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
+  D.ctr->next_id = next + B;
+  D.ctr->births = births + B;
+  if ((uint64_t)(next + B) > ID_MASK) atomicOr(&D.ctr->err, ERR_ID);
   D.nbc[0] = 0;
   *D.nreq = 0;
 }
