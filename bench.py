@@ -18,7 +18,10 @@ null-collision MCC, deposit) against HBM with the algorithmic bytes of a
 particle step: the whole particle state read and written, read cell 4 + off 4
 + v 12 + id 8, write cell 4 + off 4 + v 12 = 48 B in FP32 (80 B in FP64), times
 the particles pushed per launch, divided by the kernel's average duration from
-HIP events recorded on the library's stream around every launch.  The kernel
+HIP events recorded on the library's stream around every 8th launch of the
+timed steps (``--time-every``: the two event records add a gap of a few
+microseconds to each step they bracket, so timing every launch would slow the
+measured step; one fused-kernel launch per step).  The kernel
 itself never touches vy and vz of the ~95 % of particles that do not collide
 (the field is along x); ``achieved_touched``/``frac_touched`` count only the
 32 B (FP32; 48 B in FP64) it must move for every particle.  ``traffic`` is the
@@ -113,10 +116,12 @@ def main():
                     help="all-cores baseline: oracle instances (0: every core available to the process)")
     ap.add_argument("--warm-start-cycles", type=float, default=1.0,
                     help="large/prod/small: rf cycles run before the warm-up (the discharge's warm start)")
+    ap.add_argument("--time-every", type=int, default=8,
+                    help="HIP events around every n-th launch of the fused kernel in the timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the discharge is not sharded "
-              "across GPUs in this build.", file=sys.stderr)
+              "across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "sweep":
@@ -164,7 +169,7 @@ def main():
         print(f"[bench] {'warm start' if done <= warm else 'warmup'} {done}/{target}: "
               f"{(time.perf_counter() - tw) * 1e3 / k:.3f} ms/step, alive {m['alive']}", file=sys.stderr, flush=True)
     m0 = d.moments()
-    d.timing(True)
+    d.timing(True, every=args.time_every)
     d.sync()
     t0 = time.perf_counter()
     done = 0
@@ -187,8 +192,10 @@ def main():
           f"alive {m1['alive']}", file=sys.stderr, flush=True)
 
     bpp = BYTES_PER_STEP[args.precision]
+    # one launch of the fused kernel per step; `launches` of them timed
     avg_launch_s = (push_ms / 1e3) / max(launches, 1)
-    bytes_per_launch = bpp * psteps / max(launches, 1)
+    per_launch = psteps / args.steps
+    bytes_per_launch = bpp * per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
     # HBM bytes per launch measured by counters (FETCH_SIZE + WRITE_SIZE of
     # the same kernel in two rocprofv3 --pmc runs, calibrated against a copy
@@ -206,18 +213,18 @@ def main():
             elif t.get("source_sha") != kernel_source_sha():
                 traffic_note = "counters in profiles/ predate the current kernel sources"
             else:
-                traffic = round(t["bytes_per_push"] * psteps / max(launches, 1))
+                traffic = round(t["bytes_per_push"] * per_launch)
                 traffic_note = f"from {os.path.relpath(tfile, ROOT)} ({t['bytes_per_push']} B per push)"
         except (OSError, ValueError, KeyError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_push", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                "kernel": "k_push", "avg_launch_ms": round(avg_launch_s * 1e3, 4), "timed_launches": launches,
                 "bytes_per_push": bpp, "traffic_source": traffic_note}
     if traffic:
         roofline["achieved_traffic"] = round(traffic / avg_launch_s / 1e9, 1)
         roofline["frac_traffic"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
-    touched = BYTES_TOUCHED[args.precision] * psteps / max(launches, 1) / avg_launch_s / 1e9
+    touched = BYTES_TOUCHED[args.precision] * per_launch / avg_launch_s / 1e9
     roofline["achieved_touched"] = round(touched, 1)
     roofline["frac_touched"] = round(touched / HBM_PEAK_GBS, 4)
 

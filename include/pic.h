@@ -194,10 +194,12 @@ int pic_field(pic_ctx* ctx, double* phi_host, double* E_host);
 int pic_charge(pic_ctx* ctx, int64_t* Q_host);
 
 /*
- * Timing of the fused particle kernel: enable = 1 starts recording HIP events
- * around every launch of it on the context's stream, enable = 0 stops.
- * pic_kernel_time syncs and returns the summed duration and the launch count
- * since the last enable.
+ * Timing of the fused particle kernel: enable = k >= 1 starts recording HIP
+ * events around every k-th launch of it on the context's stream (k = 1: every
+ * launch; the two event records add a gap of a few microseconds to each step
+ * they bracket, so a larger k keeps them out of most steps), enable = 0
+ * stops; a negative value is PIC_EINVAL.  pic_kernel_time syncs and returns
+ * the summed duration and the number of timed launches since the last enable.
  */
 int pic_timing(pic_ctx* ctx, int enable);
 int pic_kernel_time(pic_ctx* ctx, double* push_ms, int64_t* launches);

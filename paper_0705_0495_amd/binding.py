@@ -230,8 +230,9 @@ class Discharge:
         self._check(self.L.pic_launch_shape(self.h, C.byref(t), C.byref(p), C.byref(g)))
         return t.value, p.value, g.value
 
-    def timing(self, enable=True):
-        self._check(self.L.pic_timing(self.h, 1 if enable else 0))
+    def timing(self, enable=True, every=1):
+        """HIP events around every `every`-th launch of the fused kernel."""
+        self._check(self.L.pic_timing(self.h, int(every) if enable else 0))
 
     def kernel_time(self):
         ms = C.c_double(0)

@@ -98,6 +98,8 @@ struct pic_ctx {
   std::string msg;
   int err = 0;
   bool timing = false;
+  int time_every = 1;        // record the events around every time_every-th launch
+  int64_t time_count = 0;    // launches of the fused kernel since timing was enabled
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t ev_used = 0;
   double timed_ms = 0;
@@ -194,6 +196,7 @@ struct Impl : Base {
   // steps each (results depend on neither), and keeps the fastest
   int autotune(int64_t steps, int32_t* chosen) override {
     const bool was = c->timing;
+    const int was_every = c->time_every;
     std::vector<std::pair<int, int>> cand;
     cand.push_back({0, grid_def[0]});
     for (int k : {1, 2, 4, 6, 8})
@@ -208,6 +211,8 @@ struct Impl : Base {
       set_shape(sg.first);
       set_grid(sg.second);
       c->timing = true;
+      c->time_every = 1;
+      c->time_count = 0;
       c->timed_ms = 0;
       c->timed_launches = 0;
       c->ev_used = 0;
@@ -221,6 +226,8 @@ struct Impl : Base {
       }
     }
     c->timing = was;
+    c->time_every = was_every;
+    c->time_count = 0;
     c->timed_ms = 0;
     c->timed_launches = 0;
     c->ev_used = 0;
@@ -712,7 +719,8 @@ struct Impl : Base {
     const int sort_every = c->G.sort_every;
     for (int64_t k = 0; k < nsteps; k++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c->timing) {
+      const bool timed = c->timing && (c->time_count++ % c->time_every) == 0;
+      if (timed) {
         if (c->ev_used == c->events.size()) {
           hipEvent_t a, b;
           HIPCHK(c, hipEventCreate(&a));
@@ -726,7 +734,7 @@ struct Impl : Base {
       }
       const Dev<R>* dpar = dD + (D.st[0].cell == dev_parity0_cell ? 0 : 1);
       launch_push(dpar);
-      if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+      if (timed) HIPCHK(c, hipEventRecord(e1, c->stream));
       HIPCHK(c, hipGetLastError());
       nstep++;
       const bool sort_now = (nstep % sort_every) == 0;
@@ -1235,10 +1243,13 @@ int pic_charge(pic_ctx* c, int64_t* Q) {
 
 int pic_timing(pic_ctx* c, int enable) {
   if (!c) return PIC_EINVAL;
+  if (enable < 0) return reject(c, "pic_timing: enable must be 0 (off) or a stride >= 1");
   if (enable) {
     c->timed_ms = 0;
     c->timed_launches = 0;
     c->ev_used = 0;
+    c->time_every = enable;
+    c->time_count = 0;
   }
   c->timing = enable != 0;
   return PIC_OK;
