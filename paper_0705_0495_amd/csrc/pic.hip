@@ -485,6 +485,7 @@ struct Impl : Base {
     if ((rc = alloc(&D.nreq, 1))) return rc;
     if ((rc = alloc(&D.ctr, 1))) return rc;
     if ((rc = alloc(&D.Qcur, 3 * (size_t)(N + 1)))) return rc;
+    if ((rc = alloc(&D.qnet, (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.Qacc, 3 * (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.Qlast, 3 * (size_t)(N + 1)))) return rc;
     if ((rc = alloc(&D.phiacc, (size_t)N + 1))) return rc;
@@ -738,7 +739,9 @@ struct Impl : Base {
       HIPCHK(c, hipGetLastError());
       nstep++;
       const bool sort_now = (nstep % sort_every) == 0;
-      HIPCHK(c, launch_serial(C, D, sort_now ? 0 : 1, c->stream));
+      // without a sort the node charge is formed by many workgroups first
+      if (!sort_now) HIPCHK(c, launch_charge(C, D, c->stream));
+      HIPCHK(c, launch_serial(C, D, sort_now ? 0 : 2, c->stream));
       if (sort_now) {
         int rc = sort();
         if (rc) return rc;

@@ -193,6 +193,7 @@ struct Dev {
   int64_t* Qcur;    // [3][Nc+1] node charge of the population the next push starts from
   int64_t* Qacc;
   int64_t* Qlast;
+  int64_t* qnet;    // [Nc+1] net node charge of the step (k_charge), read by the field solve
   double* phiacc;
   double* philast;
   int64_t* eedf_acc;
@@ -425,6 +426,35 @@ __device__ __forceinline__ void deposit_global(const Dev<R>& D, int N, int sp, i
   atomicAdd((unsigned long long*)&D.F[(size_t)sp * N + cell], (unsigned long long)(int64_t)(sign * (int64_t)f));
 }
 
+// Where a partner reaction's change of charge goes.  Without `direct` to the
+// deposit counters, from which the field is formed afterwards.  With it the
+// node charge of the step has already been formed from them (k_charge): the
+// change goes to that node charge (per species and net, and the rf-cycle
+// sums), and to the counters as well only for the ions when the next push
+// does not move them (the counters then outlive the step).
+struct ClaimDep {
+  int direct;
+  bool ion_next;  // the next push moves the ions (their counters are cleared)
+};
+
+template <class R>
+__device__ __forceinline__ void deposit_claim(const Consts<R>& C, const Dev<R>& D, int sp, int cell, R off, int sign,
+                                              ClaimDep dep) {
+  if (!dep.direct || (sp != 0 && !dep.ion_next)) deposit_global(D, C.N, sp, cell, off, sign);
+  if (!dep.direct) return;
+  const int N = C.N;
+  const int64_t f = frac24(off);
+  const int64_t a = sign * ((int64_t(1) << 24) - f), b = sign * f;
+  const int64_t qs = sp == 2 ? 1 : -1;
+  const size_t o = (size_t)sp * (N + 1) + cell;
+  atomicAdd((unsigned long long*)&D.Qcur[o], (unsigned long long)a);
+  atomicAdd((unsigned long long*)&D.Qcur[o + 1], (unsigned long long)b);
+  atomicAdd((unsigned long long*)&D.Qacc[o], (unsigned long long)a);
+  atomicAdd((unsigned long long*)&D.Qacc[o + 1], (unsigned long long)b);
+  atomicAdd((unsigned long long*)&D.qnet[cell], (unsigned long long)(qs * a));
+  atomicAdd((unsigned long long*)&D.qnet[cell + 1], (unsigned long long)(qs * b));
+}
+
 __device__ __forceinline__ int birth_bucket(uint64_t creator, uint64_t next_id) {
   const int bits = 64 - __clzll((long long)(next_id | 1));
   const int sh = bits > NBUCKET_BITS ? bits - NBUCKET_BITS : 0;
@@ -433,7 +463,7 @@ __device__ __forceinline__ int birth_bucket(uint64_t creator, uint64_t next_id) 
 
 template <class R>
 __device__ void add_birth(const Consts<R>& C, const Dev<R>& D, int sp, uint64_t creator, int k, int cell, R off,
-                          R v0, R v1, R v2) {
+                          R v0, R v1, R v2, ClaimDep dep = ClaimDep{0, false}) {
   int b = atomicAdd(&D.nbc[0], 1);
   int bs = atomicAdd(&D.nbc[1 + sp], 1);
   if (b >= D.nb_cap) {
@@ -457,7 +487,7 @@ __device__ void add_birth(const Consts<R>& C, const Dev<R>& D, int sp, uint64_t 
   }
   D.nb[b] = r;
   atomicAdd(&D.bhist[birth_bucket(r.creator, (uint64_t)D.ctr->next_id)], 1);
-  if (r.sp >= 0) deposit_global(D, C.N, sp, cell, off, 1);
+  if (r.sp >= 0) deposit_claim(C, D, sp, cell, off, 1, dep);
 }
 
 template <class R>
@@ -527,74 +557,89 @@ __device__ __forceinline__ __int128 wave_scan_i128(__int128 x) {
 }
 
 template <class R, int PER>
-__device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64_t n, FieldLds& FL) {
+__device__ void field_phase(const Consts<R>& C, const Dev<R>& D, int mode, int64_t n, FieldLds& FL,
+                            bool direct = false) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int N = C.N;
   const bool ion = (n % C.nsub) == 0;
-  // 1. node charge Q_s[i] = 2^24 cnt[i] - F[i] + F[i-1], node i = tid + k *
-  // FIELD_TPB (coalesced); F[i-1] is the left neighbour's F[i], by a shuffle
-  // inside the wave and through LDS across waves.  With the step's
-  // diagnostics (mode 1) the rf-cycle sums take one integer addition per node
-  // and step, by the thread that owns the node: this workgroup is the only
-  // writer, so a plain read-modify-write, its loads in flight with the others
-  int32_t cn[3][PER];
-  int64_t Fc[3][PER], qa[3][PER];
-#pragma unroll
-  for (int s = 0; s < 3; s++)
+  if (direct) {
+    // the net node charge of the step, formed by k_charge (partner reactions
+    // since then included)
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = tid + k * FIELD_TPB;
-      cn[s][k] = i < N ? D.cnt[s * N + i] : 0;
-      Fc[s][k] = i < N ? D.F[s * N + i] : 0;
+      if (i > N) continue;
+      const int64_t q = D.qnet[i];
+      FL.v.q[i] = q;
+      if (i == 0) FL.q0 = q;
+      if (i == N) FL.qN = q;
     }
-#pragma unroll
-  for (int s = 0; s < 3; s++)
-#pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int i = tid + k * FIELD_TPB;
-      qa[s][k] = (i <= N && mode == 1) ? D.Qacc[s * (N + 1) + i] : 0;
-    }
-  if (lane == 63) {
+  } else {
+    // 1. node charge Q_s[i] = 2^24 cnt[i] - F[i] + F[i-1], node i = tid + k *
+    // FIELD_TPB (coalesced); F[i-1] is the left neighbour's F[i], by a shuffle
+    // inside the wave and through LDS across waves.  With the step's
+    // diagnostics (mode 1) the rf-cycle sums take one integer addition per node
+    // and step, by the thread that owns the node: this workgroup is the only
+    // writer, so a plain read-modify-write, its loads in flight with the others
+    int32_t cn[3][PER];
+    int64_t Fc[3][PER], qa[3][PER];
 #pragma unroll
     for (int s = 0; s < 3; s++)
 #pragma unroll
-      for (int k = 0; k < PER; k++) FL.fb[s][k][wv] = Fc[s][k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int i = tid + k * FIELD_TPB;
-    int64_t Qs[3];
-#pragma unroll
-    for (int s = 0; s < 3; s++) {
-      int64_t left = __shfl_up(Fc[s][k], 1);
-      if (lane == 0) left = wv > 0 ? FL.fb[s][k][wv - 1] : (k > 0 ? FL.fb[s][k - 1][FIELD_TPB / 64 - 1] : 0);
-      const int64_t Fm = (i >= 1 && i <= N) ? left : 0;
-      const int64_t v = (((int64_t)cn[s][k] << 24) - Fc[s][k]) + Fm;
-      Qs[s] = v;
-      if (i <= N) {
-        D.Qcur[s * (N + 1) + i] = v;
-        if (mode == 1) D.Qacc[s * (N + 1) + i] = qa[s][k] + v;
+      for (int k = 0; k < PER; k++) {
+        const int i = tid + k * FIELD_TPB;
+        cn[s][k] = i < N ? D.cnt[s * N + i] : 0;
+        Fc[s][k] = i < N ? D.F[s * N + i] : 0;
       }
-    }
-    if (i > N) continue;
-    const int64_t q = (Qs[2] - Qs[0]) - Qs[1];
-    FL.v.q[i] = q;
-    if (i == 0) FL.q0 = q;
-    if (i == N) FL.qN = q;
-  }
-  if (mode == 1) {
-    // the passes of this step deposit every moved particle afresh
 #pragma unroll
-    for (int s = 0; s < 3; s++) {
-      if (s != 0 && !ion) continue;
+    for (int s = 0; s < 3; s++)
 #pragma unroll
       for (int k = 0; k < PER; k++) {
         const int i = tid + k * FIELD_TPB;
-        if (i < N) {
-          D.cnt[s * N + i] = 0;
-          D.F[s * N + i] = 0;
+        qa[s][k] = (i <= N && mode == 1) ? D.Qacc[s * (N + 1) + i] : 0;
+      }
+    if (lane == 63) {
+#pragma unroll
+      for (int s = 0; s < 3; s++)
+#pragma unroll
+        for (int k = 0; k < PER; k++) FL.fb[s][k][wv] = Fc[s][k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = tid + k * FIELD_TPB;
+      int64_t Qs[3];
+#pragma unroll
+      for (int s = 0; s < 3; s++) {
+        int64_t left = __shfl_up(Fc[s][k], 1);
+        if (lane == 0) left = wv > 0 ? FL.fb[s][k][wv - 1] : (k > 0 ? FL.fb[s][k - 1][FIELD_TPB / 64 - 1] : 0);
+        const int64_t Fm = (i >= 1 && i <= N) ? left : 0;
+        const int64_t v = (((int64_t)cn[s][k] << 24) - Fc[s][k]) + Fm;
+        Qs[s] = v;
+        if (i <= N) {
+          D.Qcur[s * (N + 1) + i] = v;
+          if (mode == 1) D.Qacc[s * (N + 1) + i] = qa[s][k] + v;
+        }
+      }
+      if (i > N) continue;
+      const int64_t q = (Qs[2] - Qs[0]) - Qs[1];
+      FL.v.q[i] = q;
+      if (i == 0) FL.q0 = q;
+      if (i == N) FL.qN = q;
+    }
+    if (mode == 1) {
+      // the passes of this step deposit every moved particle afresh
+#pragma unroll
+      for (int s = 0; s < 3; s++) {
+        if (s != 0 && !ion) continue;
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+          const int i = tid + k * FIELD_TPB;
+          if (i < N) {
+            D.cnt[s * N + i] = 0;
+            D.F[s * N + i] = 0;
+          }
         }
       }
     }
@@ -1495,12 +1540,12 @@ __device__ __forceinline__ bool last_block(uint32_t* counter, int grid) {
 constexpr int TAIL_TPB = 1024;
 
 template <class R>
-__device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int slot) {
+__device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int slot, ClaimDep dep = ClaimDep{0, false}) {
   const Store<R> st = D.st[sp];
   const int cell = st.cell[slot];
   if (cell == DEAD) return;
   const R off = st.off[slot];
-  deposit_global(D, C.N, sp, cell, off, -1);
+  deposit_claim(C, D, sp, cell, off, -1, dep);
   st.cell[slot] = DEAD;
 }
 
@@ -1508,7 +1553,8 @@ __device__ void kill_particle(const Consts<R>& C, const Dev<R>& D, int sp, int s
 // the O- splits into O + e (loss dE of Eq. (5)), the two electrons scatter
 // elastically; directions from the electron's stream kr
 template <class R>
-__device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int p, uint64_t id, uint32_t n, uint32_t kr) {
+__device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int p, uint64_t id, uint32_t n, uint32_t kr,
+                              ClaimDep dep = ClaimDep{0, false}) {
   const Store<R> es = D.st[0], ns = D.st[1];
   R T[3], P[3];
   T[0] = es.vx[slot];
@@ -1538,8 +1584,8 @@ __device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int
   st_yz(es, slot, ve[1], ve[2]);
   const int pc = ns.cell[p];
   const R po = ns.off[p];
-  kill_particle(C, D, 1, p);
-  add_birth(C, D, 0, id, 0, pc, po, vn[0], vn[1], vn[2]);
+  kill_particle(C, D, 1, p, dep);
+  add_birth(C, D, 0, id, 0, pc, po, vn[0], vn[1], vn[2], dep);
 }
 
 constexpr int REQ_LDS = 64;  // requests kept in LDS while they are resolved (the rest read from global memory)
@@ -1553,7 +1599,7 @@ struct ClaimLds {
 static_assert(sizeof(Request<float>) <= sizeof(Request<double>), "request slots");
 
 template <class R>
-__device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, int nr, uint32_t n) {
+__device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L, int nr, uint32_t n, ClaimDep dep) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   constexpr int NWV = TAIL_TPB / 64;
@@ -1680,11 +1726,11 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[q.chan], 1ull);
     if (q.chan == 12) {
-      kill_particle(C, D, 0, q.slot);
-      kill_particle(C, D, 2, L.rpart[r]);
+      kill_particle(C, D, 0, q.slot, dep);
+      kill_particle(C, D, 2, L.rpart[r], dep);
       continue;
     }
-    impact_detach(C, D, q.slot, L.rpart[r], q.id, n, 2);
+    impact_detach(C, D, q.slot, L.rpart[r], q.id, n, 2, dep);
   }
   __syncthreads();
   // stage 2: O- test particles (14); the O- must not have been taken by a
@@ -1718,8 +1764,8 @@ __device__ void resolve_claims(const Consts<R>& C, const Dev<R>& D, ClaimLds& L,
     const Request<R> q = req(r);
     nacc++;
     atomicAdd((unsigned long long*)&D.ctr->events[17], 1ull);
-    kill_particle(C, D, 1, q.slot);
-    kill_particle(C, D, 2, L.rpart[r]);
+    kill_particle(C, D, 1, q.slot, dep);
+    kill_particle(C, D, 2, L.rpart[r], dep);
   }
   if (nacc) atomicAdd((unsigned long long*)&D.ctr->nacc, (unsigned long long)nacc);
   if (tid == 0) atomicAdd((unsigned long long*)&D.ctr->nreq, (unsigned long long)nr);
@@ -1873,10 +1919,11 @@ __device__ void close_births(const Dev<R>& D) {
 
 // close the rf cycle: move the accumulated sums to the last-cycle buffers
 template <class R>
-__device__ void close_cycle(const Consts<R>& C, const Dev<R>& D) {
+__device__ void close_cycle(const Consts<R>& C, const Dev<R>& D, bool q_done = false) {
   const int tid = threadIdx.x;
   const int N = C.N;
-  for (int i = tid; i < 3 * (N + 1); i += TAIL_TPB) {
+  // (q_done: k_charge has closed the node-charge sums already)
+  for (int i = tid; i < 3 * (N + 1) && !q_done; i += TAIL_TPB) {
     D.Qlast[i] = D.Qacc[i];
     D.Qacc[i] = 0;
   }
@@ -1893,6 +1940,20 @@ __device__ void close_cycle(const Consts<R>& C, const Dev<R>& D) {
     D.fneg_acc[i] = 0;
   }
   if (tid == 0) D.ctr->cycles += 1;
+}
+
+// clear the deposit counters of the species the next push moves (it deposits
+// them afresh): electrons always, the ions when the next push moves them
+template <class R>
+__device__ void clear_counters(const Consts<R>& C, const Dev<R>& D, bool ion_next) {
+  const int N = C.N;
+  for (int s = 0; s < 3; s++) {
+    if (s != 0 && !ion_next) continue;
+    for (int i = threadIdx.x; i < N; i += TAIL_TPB) {
+      D.cnt[s * N + i] = 0;
+      D.F[s * N + i] = 0;
+    }
+  }
 }
 
 // End of step n, the step the push advanced.  Two workgroups: when no
@@ -1915,16 +1976,28 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
   if (nr > D.req_cap) nr = D.req_cap;
   const bool split = nr == 0 && do_field;
   const bool cyc = (n + 1) % C.M == 0;
+  // do_field 2: k_charge has formed the step's node charge from the deposit
+  // counters; the field is solved from it, the counters of the species the
+  // next push moves are cleared by the second workgroup (the partner
+  // reactions never touch those), and the reactions change the node charge
+  // directly
+  const bool direct = do_field == 2;
+  const bool ion_next = ((n + 1) % C.nsub) == 0;
+  const ClaimDep dep{direct ? 1 : 0, ion_next};
   if (blockIdx.x == 1) {
-    if (!split) return;
-    if (cyc) close_cycle(C, D);
+    if (!split) {
+      if (direct) clear_counters(C, D, ion_next);
+      return;
+    }
+    if (cyc) close_cycle(C, D, direct);
     __syncthreads();
-    field_phase<R, PER>(C, D, 1, n + 1, U.field);
+    field_phase<R, PER>(C, D, 1, n + 1, U.field, direct);
+    if (direct) clear_counters(C, D, ion_next);
     return;
   }
   // within the workgroup, barriers order the global writes of one phase
   // before the reads of the next (no device-scope fence needed)
-  if (nr > 0) resolve_claims(C, D, U.claims, nr, (uint32_t)n);
+  if (nr > 0) resolve_claims(C, D, U.claims, nr, (uint32_t)n, dep);
   __syncthreads();
   births_phase(C, D, U.cur, part, bkeys);
   __syncthreads();
@@ -1933,10 +2006,10 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
     D.ctr->step = n + 1;
   }
   if (split) return;
-  if (cyc) close_cycle(C, D);
+  if (cyc) close_cycle(C, D, direct);
   if (!do_field) return;
   __syncthreads();
-  field_phase<R, PER>(C, D, 1, n + 1, U.field);
+  field_phase<R, PER>(C, D, 1, n + 1, U.field, direct);
 }
 
 template <class R, int PER>
@@ -1962,6 +2035,49 @@ inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_fiel
     case 6: case 7: hipLaunchKernelGGL((k_serial<R, 7>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
     default: hipLaunchKernelGGL((k_serial<R, FIELD_PER_MAX>), dim3(2), dim3(TAIL_TPB), 0, st, C, D, do_field); break;
   }
+  return hipGetLastError();
+}
+
+// The node charge of step n+1 from the deposit counters, one thread per node
+// (many workgroups, so that the single-workgroup field solve only reads the
+// net charge): per species into Qcur and the rf-cycle sums (the cycle's sum
+// moved to Qlast at its end), net into qnet.  The counters are only read.
+constexpr int CHARGE_TPB = 256;
+template <class R>
+__global__ void __launch_bounds__(CHARGE_TPB) k_charge(Consts<R> C, Dev<R> D) {
+  const int N = C.N;
+  const int i = (int)blockIdx.x * CHARGE_TPB + (int)threadIdx.x;
+  if (i > N) return;
+  const bool cyc = (D.ctr->step_push + 1) % C.M == 0;
+  int32_t cn[3];
+  int64_t Fc[3], Fm[3], qa[3];
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    cn[s] = i < N ? D.cnt[s * N + i] : 0;
+    Fc[s] = i < N ? D.F[s * N + i] : 0;
+    Fm[s] = i >= 1 ? D.F[s * N + i - 1] : 0;
+    qa[s] = D.Qacc[s * (N + 1) + i];
+  }
+  int64_t Qs[3];
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    const int64_t v = (((int64_t)cn[s] << 24) - Fc[s]) + Fm[s];
+    Qs[s] = v;
+    const int o = s * (N + 1) + i;
+    D.Qcur[o] = v;
+    if (cyc) {
+      D.Qlast[o] = qa[s];
+      D.Qacc[o] = v;
+    } else {
+      D.Qacc[o] = qa[s] + v;
+    }
+  }
+  D.qnet[i] = (Qs[2] - Qs[0]) - Qs[1];
+}
+
+template <class R>
+inline hipError_t launch_charge(const Consts<R>& C, const Dev<R>& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_charge<R>, dim3((C.N + 1 + CHARGE_TPB - 1) / CHARGE_TPB), dim3(CHARGE_TPB), 0, st, C, D);
   return hipGetLastError();
 }
 
