@@ -210,6 +210,9 @@ def main():
             t = json.load(open(tfile))
             if t.get("workload") != args.workload or t.get("precision") != args.precision:
                 traffic_note = "no counter file for this workload"
+            elif args.dsmc:
+                # the counters were taken with the null-collision MCC in the push
+                traffic_note = "no counter file for the push kernel of the per-cell list"
             elif t.get("source_sha") != kernel_source_sha():
                 traffic_note = "counters in profiles/ predate the current kernel sources"
             else:
