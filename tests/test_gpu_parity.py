@@ -132,6 +132,35 @@ def test_one_rf_cycle_diagnostics_match_oracle():
     assert np.array_equal(m["phi"], phi / wl.steps_per_period)
 
 
+def test_rf_cycle_closing_between_sorts_matches_oracle():
+    """Sort every 7 steps, so that the rf cycle (1000 steps) closes in a step
+    without a sort, where the node charge of the step is formed outside the
+    end-of-step kernel; partner reactions boosted so that they change the
+    charge around it.  One cycle and three steps."""
+    wl = dataclasses.replace(workload("small"), sort_every=7, coulomb_every=7)
+    sig, thr, loss = build_tables(partner_boost=PARTNER_BOOST)
+    g = _gpu()(wl, sig, thr, loss, precision="fp32")
+    o = O.Oracle(wl, sig, thr, loss, precision="fp32")
+    n = wl.steps_per_period + 3
+    g.step(n)
+    o.step(n)
+    compare(g, o, "fp32", "one cycle and 3 steps, sort every 7")
+    m = g.moments()
+    Q, phi, eedf, fneg = o.cycle_sums()
+    assert m["cycles"] == 1
+    assert np.array_equal(m["eedf"], eedf)
+    assert np.array_equal(m["fneg"], fneg)
+    dx = wl.gap_m / wl.n_cells
+    vol = np.full(wl.n_cells + 1, wl.area_m2 * dx)
+    vol[0] *= 0.5
+    vol[-1] *= 0.5
+    dens = wl.weight * (Q / 16777216.0) / vol / wl.steps_per_period
+    assert np.allclose(m["density"], dens, rtol=1e-14, atol=0)
+    assert np.array_equal(m["phi"], phi / wl.steps_per_period)
+    ev = o.counters()[0]
+    assert ev[12] > 0 or ev[13] > 0 or ev[17] > 0, ev
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_results_independent_of_launch_shape(prec):
     """Tile shapes (threads per workgroup x particles per thread) and
