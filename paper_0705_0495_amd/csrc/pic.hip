@@ -976,7 +976,9 @@ int batch_run(pic_ctx* const* ctx, int n, int64_t steps, char* buf, size_t tab_c
     hipError_t e = launch_push_b<R>(dC, dD[par], n, g, elds, bshape, st);
     nstep++;
     const bool sort_now = nstep % sort_every == 0;
-    if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, true, sort_now ? 0 : 1, st);
+    // without a sort the node charge is formed by many workgroups first
+    if (e == hipSuccess && !sort_now) e = launch_charge_b<R>(dC, dD[par], n, maxN, st);
+    if (e == hipSuccess) e = launch_tail_b<R>(dC, dD[par], n, per, true, sort_now ? 0 : 2, st);
     if (sort_now && e == hipSuccess) {
       e = launch_sort_b<R>(dC, dD[par], n, g, st);
       par ^= 1;

@@ -2044,10 +2044,10 @@ inline hipError_t launch_serial(const Consts<R>& C, const Dev<R>& D, int do_fiel
 // moved to Qlast at its end), net into qnet.  The counters are only read.
 constexpr int CHARGE_TPB = 256;
 template <class R>
-__global__ void __launch_bounds__(CHARGE_TPB) k_charge(Consts<R> C, Dev<R> D) {
+__device__ __forceinline__ void k_charge_body(const Consts<R>& C, const Dev<R>& D, int bx) {
   const int N = C.N;
-  const int i = (int)blockIdx.x * CHARGE_TPB + (int)threadIdx.x;
-  if (i > N) return;
+  const int i = bx * CHARGE_TPB + (int)threadIdx.x;
+  if (i > N) return;  // (batches launch for their largest grid)
   const bool cyc = (D.ctr->step_push + 1) % C.M == 0;
   int32_t cn[3];
   int64_t Fc[3], Fm[3], qa[3];
@@ -2076,8 +2076,27 @@ __global__ void __launch_bounds__(CHARGE_TPB) k_charge(Consts<R> C, Dev<R> D) {
 }
 
 template <class R>
+__global__ void __launch_bounds__(CHARGE_TPB) k_charge(Consts<R> C, Dev<R> D) {
+  k_charge_body<R>(C, D, (int)blockIdx.x);
+}
+
+// the same for a batch of discharges, one per blockIdx.y
+template <class R>
+__global__ void __launch_bounds__(CHARGE_TPB) k_charge_b(const Consts<R>* __restrict__ Cs,
+                                                          const Dev<R>* __restrict__ Ds) {
+  k_charge_body<R>(Cs[blockIdx.y], Ds[blockIdx.y], (int)blockIdx.x);
+}
+
+template <class R>
 inline hipError_t launch_charge(const Consts<R>& C, const Dev<R>& D, hipStream_t st) {
   hipLaunchKernelGGL(k_charge<R>, dim3((C.N + 1 + CHARGE_TPB - 1) / CHARGE_TPB), dim3(CHARGE_TPB), 0, st, C, D);
+  return hipGetLastError();
+}
+
+// maxN: the largest grid of the batch
+template <class R>
+inline hipError_t launch_charge_b(const Consts<R>* C, const Dev<R>* D, int nd, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_charge_b<R>, dim3((maxN + 1 + CHARGE_TPB - 1) / CHARGE_TPB, nd), dim3(CHARGE_TPB), 0, st, C, D);
   return hipGetLastError();
 }
 
