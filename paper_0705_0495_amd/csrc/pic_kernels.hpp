@@ -1561,6 +1561,8 @@ __device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int
   ld_yz(es, slot, T[1], T[2]);
   P[0] = ns.vx[p];
   ld_yz(ns, p, P[1], P[2]);
+  const int pc = ns.cell[p];  // the O-'s place, loaded with the velocities
+  const R po = ns.off[p];
   const R a = C.a_c[1], b = C.b_c[1];
   const R gx = T[0] - P[0], gy = T[1] - P[1], gz = T[2] - P[2];
   const R g2 = (gx * gx + gy * gy) + gz * gz;
@@ -1582,9 +1584,10 @@ __device__ void impact_detach(const Consts<R>& C, const Dev<R>& D, int slot, int
   ee_elastic<R>(ve, vn, n2);
   es.vx[slot] = ve[0];
   st_yz(es, slot, ve[1], ve[2]);
-  const int pc = ns.cell[p];
-  const R po = ns.off[p];
-  kill_particle(C, D, 1, p, dep);
+  if (pc != DEAD) {  // the O- is removed (as kill_particle does, its place known)
+    deposit_claim(C, D, 1, pc, po, -1, dep);
+    ns.cell[p] = DEAD;
+  }
   add_birth(C, D, 0, id, 0, pc, po, vn[0], vn[1], vn[2], dep);
 }
 
@@ -1978,9 +1981,9 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
   const bool cyc = (n + 1) % C.M == 0;
   // do_field 2: k_charge has formed the step's node charge from the deposit
   // counters; the field is solved from it, the counters of the species the
-  // next push moves are cleared by the second workgroup (the partner
-  // reactions never touch those), and the reactions change the node charge
-  // directly
+  // next push moves are cleared by the workgroup that does not solve the
+  // field (the partner reactions never touch those), and the reactions
+  // change the node charge directly
   const bool direct = do_field == 2;
   const bool ion_next = ((n + 1) % C.nsub) == 0;
   const ClaimDep dep{direct ? 1 : 0, ion_next};
@@ -1992,7 +1995,6 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
     if (cyc) close_cycle(C, D, direct);
     __syncthreads();
     field_phase<R, PER>(C, D, 1, n + 1, U.field, direct);
-    if (direct) clear_counters(C, D, ion_next);
     return;
   }
   // within the workgroup, barriers order the global writes of one phase
@@ -2005,7 +2007,11 @@ __device__ __forceinline__ void k_serial_body(const Consts<R>& C, const Dev<R>& 
     close_births(D);
     D.ctr->step = n + 1;
   }
-  if (split) return;
+  if (split) {
+    // the field is the other workgroup's, which reads only the net charge
+    if (direct) clear_counters(C, D, ion_next);
+    return;
+  }
   if (cyc) close_cycle(C, D, direct);
   if (!do_field) return;
   __syncthreads();
